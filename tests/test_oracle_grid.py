@@ -1,0 +1,155 @@
+"""Pins of the oracle's geometry, grid, Hilbert ordering and neighbour tables
+against facts fixed outside the oracle: Table I's atom counts, closed-form
+properties of Hilbert curves, brute-force lookups."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import grid as G
+from synth.cluster import (A_SI_OPTIMISED, make_cluster, silicon_cluster_counts, n_states,
+                           BOHR_ANGSTROM)
+
+
+# Table I of the paper lists (N_Si, N_H) per nanocluster.  With an atom-centred
+# sphere, two-neighbour pruning and one H per dangling bond, four of its rows
+# are reproduced exactly; each row holds on an interval of R / a, and the
+# midpoints are used.  (Rows Si1947H604 and Si10869H1924 are not reproducible
+# by this rule and are not pins.)
+TABLE_I = [((4.91808 + 4.94975) / 2, 4001, 1012),
+           ((8.84237 + 8.86002) / 2, 23049, 3220),
+           ((11.51086 + 11.51901) / 2, 51071, 5484)]
+
+
+@pytest.mark.parametrize("r_over_a,n_si,n_h", TABLE_I)
+def test_table_i_counts(r_over_a, n_si, n_h):
+    si, dangling = silicon_cluster_counts(r_over_a)
+    assert (len(si), len(dangling)) == (n_si, n_h)
+
+
+@pytest.mark.slow
+def test_table_i_largest():
+    si, dangling = silicon_cluster_counts((14.75424 + 14.76482) / 2)
+    assert (len(si), len(dangling)) == (107641, 9084)
+
+
+def test_table_i_diameters():
+    # at a = 5.38 angstrom the four reproduced rows' diameters are 5.3, 9.6, 12.5, 16.0 nm
+    for (r, _, _), d in zip(TABLE_I, (5.3, 9.6, 12.5)):
+        assert abs(2 * r * A_SI_OPTIMISED / 10 - d) < 0.15
+
+
+def test_hydrogen_count_is_missing_bonds():
+    c = make_cluster(5.5, 1, sigma_angstrom=0.0)
+    si = c.pos0[c.species == 0]
+    h = c.pos0[c.species == 1]
+    d_nn = 5.43 / 4 * math.sqrt(3) / BOHR_ANGSTROM
+    dist = np.sqrt(((si[:, None] - si[None]) ** 2).sum(-1))
+    nn = ((np.abs(dist - d_nn) < 1e-6).sum(1))
+    assert (nn >= 2).all()
+    assert len(h) == int((4 - nn).sum())
+    # every H sits 1.48 angstrom from exactly one Si
+    dh = np.sqrt(((h[:, None] - si[None]) ** 2).sum(-1)) * BOHR_ANGSTROM
+    assert np.allclose(np.sort(dh, 1)[:, 0], 1.48)
+    assert (np.sort(dh, 1)[:, 1] > 2.0).all()
+
+
+def test_states_are_multiples_of_64():
+    # Table I's state counts are all multiples of 64 and exceed the occupied count
+    for n_si, n_h, m in [(4001, 1012, 9216), (107641, 9084, 245760)]:
+        assert m % 64 == 0 and m >= (4 * n_si + n_h) // 2
+    assert n_states(4 * 35 + 36) == 128
+
+
+def test_perturbation_is_seeded():
+    a = make_cluster(5.5, 7)
+    b = make_cluster(5.5, 7)
+    c = make_cluster(5.5, 8)
+    assert np.array_equal(a.pos, b.pos) and not np.array_equal(a.pos, c.pos)
+    assert np.allclose(np.std((a.pos - a.pos0) * BOHR_ANGSTROM), 0.02, rtol=0.3)
+
+
+# ---------------------------------------------------------------------------
+# Hilbert curve
+# ---------------------------------------------------------------------------
+def _curve(nbits):
+    n = 1 << nbits
+    g = np.arange(n)
+    x, y, z = [a.ravel() for a in np.meshgrid(g, g, g, indexing="ij")]
+    idx = G.hilbert_index3(x, y, z, nbits)
+    order = np.argsort(idx)
+    return idx, np.stack([x[order], y[order], z[order]], 1)
+
+
+@pytest.mark.parametrize("nbits", [1, 2, 3, 4])
+def test_hilbert_bijection_and_unit_steps(nbits):
+    idx, cells = _curve(nbits)
+    assert np.array_equal(np.sort(idx), np.arange(8 ** nbits))
+    step = np.abs(np.diff(cells, axis=0)).sum(1)
+    assert (step == 1).all()
+    assert (cells[0] == 0).all()
+
+
+@pytest.mark.parametrize("nbits", [2, 3, 4])
+def test_hilbert_aligned_runs_fill_cubes(nbits):
+    _, cells = _curve(nbits)
+    for k in range(1, nbits):
+        run = 8 ** k
+        for s in range(0, len(cells), run):
+            c = cells[s:s + run]
+            ext = c.max(0) - c.min(0)
+            assert (ext == (1 << k) - 1).all()
+            assert (c.min(0) % (1 << k) == 0).all()
+
+
+def test_hilbert_order1_is_gray_walk():
+    _, cells = _curve(1)
+    gray = [i ^ (i >> 1) for i in range(8)]
+    expect = np.array([[(g >> 2) & 1, (g >> 1) & 1, g & 1] for g in gray])
+    assert np.array_equal(cells, expect)
+
+
+def test_sphere_grid_counts_and_membership():
+    g = G.build_grid(4.3, 0.7)
+    thr = math.floor((4.3 / 0.7) ** 2 + 1e-9)
+    brute = sum(1 for i in range(-7, 8) for j in range(-7, 8) for k in range(-7, 8)
+                if i * i + j * j + k * k <= thr)
+    assert g.n == brute
+    assert len({tuple(p) for p in g.ijk.tolist()}) == g.n
+
+
+@pytest.mark.parametrize("ordering", [G.ORDER_HILBERT, G.ORDER_LEX])
+def test_ordering_layout(ordering):
+    g = G.build_grid(9.1, 0.7, ordering)
+    assert np.all(np.diff(g.row_of_rank) > 0)
+    assert g.row_of_rank[-1] < g.n_rows
+    if ordering == G.ORDER_LEX:
+        key = g.ijk[:, 2] * 10 ** 6 + g.ijk[:, 1] * 10 ** 3 + g.ijk[:, 0]
+        assert np.all(np.diff(key) > 0)
+    else:
+        I = g.ijk + g.n_r
+        slot = g.row_of_rank // 512
+        assert np.array_equal(g.blocks[slot], I // 8)
+        local = g.row_of_rank % 512
+        assert np.array_equal(local, I[:, 0] % 8 + 8 * (I[:, 1] % 8) + 64 * (I[:, 2] % 8))
+        # consecutive blocks along the curve are face neighbours or at least close
+        nb = (2 * g.n_r) // 8 + 1
+        key = G.hilbert_index3(g.blocks[:, 0], g.blocks[:, 1], g.blocks[:, 2], G.hilbert_bits(nb))
+        assert np.all(np.diff(key) > 0)
+
+
+def test_neighbour_table_brute_force():
+    g = G.build_grid(5.0, 0.7)
+    nbr = G.neighbour_table(g)
+    lookup = {tuple(p): r for r, p in enumerate(g.ijk.tolist())}
+    for r, p in enumerate(g.ijk.tolist()):
+        for c, (axis, k) in enumerate(G.offsets()):
+            q = list(p)
+            q[axis] += k
+            assert nbr[r, c] == lookup.get(tuple(q), -1)
+
+
+def test_offsets_order():
+    off = G.offsets()
+    assert off[0] == (0, -6) and off[5] == (0, -1) and off[6] == (0, 1) and off[11] == (0, 6)
+    assert off[12] == (1, -6) and off[35] == (2, 6)

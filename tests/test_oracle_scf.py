@@ -1,0 +1,145 @@
+"""Pins of the oracle's SCF pieces: multipole harmonics against the Legendre
+addition theorem, the Poisson solver against the analytic potential of
+Gaussian charges, LDA potentials against numerical derivatives of the
+energy density, Anderson mixing on a linear fixed point, and a small SCF
+whose converged eigenvalues are those of its own final Hamiltonian."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf, eval_legendre
+
+from oracle import grid as G
+from oracle import hamiltonian as OH
+from oracle import scf as S
+from synth.cluster import BOHR_ANGSTROM, random_block
+
+
+def test_solid_harmonics_addition_theorem():
+    rng = np.random.default_rng(0)
+    a, b = rng.standard_normal((2, 3, 50))
+    Ra = S.solid_harmonics(*a)
+    Rb = S.solid_harmonics(*b)
+    na = np.sqrt((a ** 2).sum(0))
+    nb = np.sqrt((b ** 2).sum(0))
+    cosg = (a * b).sum(0) / (na * nb)
+    for l in range(5):
+        sel = S.SH_L == l
+        lhs = (Ra[sel] * Rb[sel]).sum(0)
+        rhs = na ** l * nb ** l * eval_legendre(l, cosg)
+        assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+def _gauss(g, centre, s, q):
+    d2 = ((g.xyz - centre) ** 2).sum(1)
+    return q * (2 * math.pi * s * s) ** -1.5 * np.exp(-d2 / (2 * s * s))
+
+
+@pytest.mark.parametrize("centre", [(0.0, 0.0, 0.0), (0.9, -0.6, 0.5)])
+def test_poisson_gaussian_charge(centre):
+    g = G.build_grid(9.0, 0.45)
+    nbr = G.neighbour_table(g)
+    lap = OH.laplacian(g, nbr)
+    s, q = 1.1, 2.0
+    rho = _gauss(g, np.array(centre), s, q)
+    v, it = S.hartree(g, lap, nbr, rho)
+    d = np.sqrt(((g.xyz - np.array(centre)) ** 2).sum(1))
+    exact = q * erf(d / (math.sqrt(2) * s)) / np.where(d > 0, d, 1)
+    exact = np.where(d > 0, exact, q * math.sqrt(2 / math.pi) / s)
+    assert np.abs(v - exact).max() < 2e-4 * exact.max()
+    # the discrete residual of the solve is tiny by construction
+    assert it > 10
+
+
+def test_multipole_potential_exterior():
+    g = G.build_grid(7.0, 0.4)
+    c = np.array([0.8, 0.3, -0.5])
+    rho = _gauss(g, c, 0.7, 1.5)
+    q = S.multipole_moments(g, rho)
+    pts = np.array([[9.0, 0.0, 0.0], [0.0, -8.5, 3.0], [5.0, 5.0, 5.0]])
+    v = S.multipole_potential(q, pts)
+    exact = 1.5 / np.sqrt(((pts - c) ** 2).sum(1))
+    assert np.allclose(v, exact, rtol=5e-5)
+
+
+def test_lda_potential_is_derivative():
+    rho = np.array([1e-4, 3e-3, 0.02, 0.07, 0.2, 0.5, 2.0])
+    eps, v = S.lda(rho)
+    d = 1e-6 * rho
+    ep, _ = S.lda(rho + d)
+    em, _ = S.lda(rho - d)
+    num = ((rho + d) * ep - (rho - d) * em) / (2 * d)
+    assert np.allclose(v, num, rtol=1e-7)
+    # exchange part: -(3/4)(3 rho / pi)^(1/3)
+    rs = (3 / (4 * math.pi * rho)) ** (1 / 3)
+    ex = -0.75 * (3 * rho / math.pi) ** (1 / 3)
+    assert np.allclose(eps - S.lda_eps(rs) + (-S.EX_CONST / rs) - ex, 0.0, atol=1e-14)
+    # the two correlation branches nearly meet at r_s = 1
+    lo = S.PZ_A * 0 + S.PZ_B + 0 + S.PZ_D
+    hi = S.PZ_GAMMA / (1 + S.PZ_BETA1 + S.PZ_BETA2)
+    assert abs(lo - hi) < 2e-4
+    assert np.all(S.lda(np.array([0.0, 1e-15, -1e-3]))[1] == 0.0)
+
+
+def test_anderson_solves_linear_fixed_point():
+    rng = np.random.default_rng(1)
+    n = 5
+    A = rng.standard_normal((n, n))
+    A = 0.3 * A / np.linalg.norm(A, 2)
+    c = rng.standard_normal(n)
+    x_star = np.linalg.solve(np.eye(n) - A, c)
+    mix = S.Anderson(beta=0.3, history=6)
+    x = np.zeros(n)
+    for _ in range(8):
+        x = mix.mix(x, A @ x + c - x)
+    assert np.allclose(x, x_star, atol=1e-10)
+
+
+def test_ion_energy_pair():
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 3.0, 4.0], [1.0, 0.0, 0.0]])
+    z = np.array([4.0, 1.0, 1.0])
+    expect = 4 / 5 + 4 / 1 + 1 / math.sqrt(1 + 9 + 16)
+    assert abs(S.ion_energy(pos, z) - expect) < 1e-14
+
+
+def test_sad_density_normalised():
+    g = G.build_grid(9.0, 0.7)
+    rho = S.sad_density(g, np.array([[0.0, 0, 0], [2.8, 0, 0]]), np.array([0, 1], np.int32), 5)
+    assert abs(g.h ** 3 * rho.sum() - 5) < 1e-12 and (rho > 0).all()
+
+
+@pytest.fixture(scope="module")
+def sih4_scf():
+    d = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
+    pos = np.array([[0, 0, 0], [d, d, d], [d, -d, -d], [-d, d, -d], [-d, -d, d]], float)
+    species = np.array([0, 1, 1, 1, 1], np.int32)
+    g = G.build_grid(float(np.sqrt((pos ** 2).sum(1)).max()) + 5.0, 0.7)
+    nbr = G.neighbour_table(g)
+    pp = OH.PseudoParams()
+    H = OH.build_hamiltonian(g, pos, species, pp)
+    st = S.ScfState(S.sad_density(g, pos, species, 8), random_block(g.n, 10, 5), np.zeros(g.n))
+    eii = S.ion_energy(pos, pp.charges(species))
+    reps = [S.scf_step(H, nbr, st, 8, 12, random_block(g.n, 1, 6)[:, 0], eii) for _ in range(30)]
+    return H, nbr, st, reps
+
+
+def test_scf_converges_and_is_self_consistent(sih4_scf):
+    H, nbr, st, reps = sih4_scf
+    assert reps[-1].sre_ry < 1e-4
+    assert reps[0].sre_ry > 1e-2
+    # the tracked eigenvalues are those of the final Hamiltonian (V built from rho_in)
+    lam = np.linalg.eigvalsh(H.dense())
+    assert np.allclose(reps[-1].eig[:4], lam[:4], atol=1e-8)
+    assert reps[-1].lumo - reps[-1].homo > 0.05
+    # Harris-Foulkes energy settles
+    assert abs(reps[-1].energy - reps[-2].energy) < 1e-7
+
+
+def test_scf_energy_stationary(sih4_scf):
+    # near self-consistency the Harris-Foulkes functional is stationary: the
+    # SRE-weighted change of energy is second order
+    _, _, _, reps = sih4_scf
+    e = np.array([r.energy for r in reps])
+    sre = np.array([r.sre_ry for r in reps])
+    late = slice(10, None)
+    assert np.all(np.abs(e[late] - e[-1]) < 10 * sre[late] ** 2 + 1e-8)
