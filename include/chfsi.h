@@ -1,0 +1,277 @@
+/*
+ * chfsi.h -- C ABI of the MI355X (gfx950) Chebyshev-filtered subspace
+ * iteration library for real-space finite-difference Kohn-Sham DFT.
+ *
+ * The method: the Kohn-Sham Hamiltonian H = -1/2 Laplacian + V_eff + separable
+ * Kleinman-Bylander projectors is discretised by a high-order (12th-order)
+ * finite-difference stencil on a spherical real-space grid whose points are
+ * stored along blockwise Hilbert space-filling curves; the lowest eigen-
+ * subspace is tracked by Chebyshev-filtered subspace iteration (filter, then
+ * Cholesky-QR orthonormalisation, then Rayleigh-Ritz), updated together with
+ * the potential over the self-consistent-field (SCF) steps: four ChFSI
+ * iterations in the first SCF step, one in each later step, until the
+ * self-consistent residual error drops below 1e-4 Ry.
+ * (Paper: the CheFSI paragraph, the sparse-product / space-filling-curve
+ * paragraph, the computational-details paragraph and Table I.)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: bohr and hartree.
+ * Status: every call returns 0 (CHF_OK) or a negative CHF_E* code and never
+ *   throws or aborts across the ABI; chf_last_error() returns a thread-local
+ *   message for the last failing call on the calling thread.
+ * Memory: all arrays named *_dev live in device memory and are owned by the
+ *   caller; arrays named *_host live in host memory.  Handles own their
+ *   internal tables until *_destroy.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *   asynchronous on that stream except where they return values in host
+ *   memory, which synchronise the stream before returning.
+ * Vector blocks: a block of nvec vectors is row-major [n_rows][ld] in the
+ *   Hamiltonian's row order (see ham_export_ordering), vectors contiguous
+ *   within a row, ld >= nvec.  Rows that hold no grid point (padding of the
+ *   8^3 Hilbert blocks) must be zero on input and stay zero.  Orthonormality
+ *   is Euclidean (X^T X = I, no h^3 factor).
+ * Precision: CHF_F32 blocks are float, CHF_F64 blocks are double; the
+ *   arithmetic of a call runs in that precision unless stated otherwise.
+ * Errors: arguments are validated on the host before any launch (CHF_EINVAL);
+ *   device failures map to CHF_EHIP.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHF_OK 0
+#define CHF_EINVAL (-1)        /* bad argument (null, size, alignment, ld)        */
+#define CHF_ENOMEM (-2)        /* device or host allocation failed               */
+#define CHF_EHIP (-3)          /* HIP runtime / library error                    */
+#define CHF_ENOTPD (-4)        /* Gram matrix not positive definite              */
+#define CHF_ENOTCONV (-5)      /* iteration limit reached                        */
+#define CHF_ENONFINITE (-6)    /* NaN or Inf met in an input or result           */
+#define CHF_EUNSUPPORTED (-7)  /* valid request this build does not provide      */
+
+typedef enum { CHF_F32 = 1, CHF_F64 = 2 } chf_dtype;
+
+typedef enum { CHF_ORDER_HILBERT = 0, CHF_ORDER_LEX = 1 } chf_ordering;
+
+typedef struct chf_ctx chf_ctx;
+typedef struct chf_ham chf_ham;
+typedef struct chf_scf chf_scf;
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* chf_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Context: rocBLAS / rocSOLVER handles and the M x M FP64 scratch used by the
+ * dense subspace steps.  The scratch grows on demand (device allocation on
+ * the first call that needs more) and is freed by chf_ctx_destroy.
+ * ------------------------------------------------------------------------- */
+int chf_ctx_create(int device, chf_ctx** out);
+int chf_ctx_destroy(chf_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Hamiltonian construction (paper: the real-space finite-difference
+ * discretisation, the spherical confined domain, the KB-form
+ * pseudopotentials, and the blockwise Hilbert space-filling curves).
+ *
+ * Grid points: (i, j, k) * h with i^2 + j^2 + k^2 <= floor((radius / h)^2 +
+ * 1e-9), origin at the centre atom.  ordering = CHF_ORDER_HILBERT: 8^3 blocks
+ * counted from the bounding-box minimum corner, ordered by a 3-D Hilbert
+ * index (Skilling's transpose algorithm, x the most significant axis), points
+ * x-fastest inside a block, row = block slot * 512 + local index (padded).
+ * ordering = CHF_ORDER_LEX: z-slowest, x-fastest over inside points, row =
+ * rank (no padding).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double h;          /* grid spacing (bohr), > 0                                 */
+    double radius;     /* domain radius (bohr), > h                                */
+    int ordering;      /* chf_ordering                                             */
+    int keep_nbr;      /* nonzero: keep the per-row 36-neighbour table on device   */
+                       /* (always kept for CHF_ORDER_LEX)                          */
+    int dtypes;        /* bit mask of precisions to prepare: 1 = F32, 2 = F64      */
+} chf_grid_desc;
+
+typedef struct {
+    int n_atoms;
+    const double* pos_host;      /* [n_atoms][3] bohr                                */
+    const int* species_host;     /* [n_atoms]; 0 = Si (KB projectors), 1 = H         */
+} chf_atoms;
+
+/* Model pseudopotential: V_loc(r) = -sum_a Z_a erf(|r - R_a| / r_loc_a) /
+ * |r - R_a| (finite r -> 0 limit), one s and one p Gaussian projector per Si
+ * p_l(r) = N_l r^l exp(-r^2 / (2 r_c^2)) (int p_l^2 r^2 dr = 1) times real
+ * harmonics, cut at |r - R_a| <= r_cut, KB energies h_s and h_p. */
+typedef struct {
+    double z_si, z_h;            /* ionic charges                                    */
+    double r_loc_si, r_loc_h;    /* erf widths of the local part                     */
+    double r_c, r_cut;           /* projector width and cutoff radius                */
+    double h_s, h_p;             /* KB energies (Ha)                                 */
+} chf_pp;
+
+/* Builds the grid, the ordering, the neighbour and block tables, the
+ * projector tables (host), uploads them, and computes V_loc on the device in
+ * FP64; V_eff starts equal to V_loc.  The handle is bound to the device that
+ * is current at the call. */
+int ham_build(const chf_grid_desc* grid, const chf_atoms* atoms, const chf_pp* pp,
+              void* stream, chf_ham** out);
+
+/* Host-only construction of the same ordering (no device needed): fills
+ * *n_points and *n_rows; when the arrays are non-NULL also ijk_host
+ * [n_points][3], row_of_rank_host [n_points] and nbr_host [n_points][36]
+ * (neighbour ranks, -1 outside) -- call once with NULL arrays to size them. */
+int chf_ordering_host(const chf_grid_desc* grid, int64_t* n_points, int64_t* n_rows, int32_t* ijk_host,
+                      int64_t* row_of_rank_host, int32_t* nbr_host);
+
+/* Host-only projector tables: *n_pairs (point, Si) pairs; when non-NULL,
+ * sup_off_host [n_Si + 1] offsets, sup_rank_host [n_pairs] point ranks
+ * (ascending within an atom), sup_beta_host [n_pairs][4] (s, px, py, pz)
+ * projector values without the h^3 or KB-energy factors. */
+int chf_projectors_host(const chf_grid_desc* grid, const chf_atoms* atoms, const chf_pp* pp, int64_t* n_pairs,
+                        int64_t* sup_off_host, int32_t* sup_rank_host, double* sup_beta_host);
+int ham_destroy(chf_ham* ham);
+
+/* n_points: grid points inside the sphere; n_rows: rows of a vector block
+ * (>= n_points); n_blocks: occupied 8^3 blocks (0 for CHF_ORDER_LEX);
+ * n_proj: KB projector atoms; n_pairs: (point, projector atom) pairs. */
+int ham_info(const chf_ham* ham, int64_t* n_points, int64_t* n_rows, int64_t* n_blocks,
+             int64_t* n_proj, int64_t* n_pairs);
+
+/* Host copies of the ordering, by rank (curve order of the points):
+ * ijk_host [n_points][3] integer coordinates; row_of_rank_host [n_points];
+ * nbr_host [n_points][36] neighbour ranks or -1 (offsets axis-major x, y, z,
+ * each -6..-1 then +1..+6).  Any pointer may be NULL. */
+int ham_export_ordering(const chf_ham* ham, int32_t* ijk_host, int64_t* row_of_rank_host,
+                        int32_t* nbr_host);
+
+/* V_loc on the rows (FP64, [n_rows], padding rows 0) into vloc_dev. */
+int ham_get_vloc(const chf_ham* ham, double* vloc_dev, void* stream);
+
+/* Sets V_eff from veff_dev (FP64 [n_rows]); padding rows are ignored.  FP32
+ * copies are derived on the device.  Returns CHF_ENONFINITE (and leaves the
+ * previous V_eff) if any inside value is NaN or Inf. */
+int ham_set_veff(chf_ham* ham, const double* veff_dev, void* stream);
+
+/* Y = H X for nvec vectors (paper: the sparse matrix-vector products on which
+ * ChFSI's efficiency rests).  X and Y must not overlap.  Uses the handle's
+ * KB-coefficient scratch (grown on demand). */
+int ham_apply(chf_ham* ham, chf_dtype dtype, const void* X_dev, int64_t ldx, void* Y_dev,
+              int64_t ldy, int nvec, void* stream);
+
+/* Degree-m scaled Chebyshev filter (paper: the CheFSI paragraph; the Zhou-Saad
+ * form): X <- T_m((H - c) / e) X / T_m((a0 - c) / e), e = (b - a) / 2,
+ * c = (b + a) / 2, evaluated by the three-term recurrence in place over X and
+ * work (work: [n_rows][ldw], ldw >= nvec, same dtype; its contents on return
+ * are unspecified).  Requires a < b and a0 < a; degree >= 1. */
+int chebyshev_filter(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
+                     double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
+
+/* The same operator and filter forced onto the neighbour-table kernel (needs
+ * keep_nbr): a layout-independent second device path used to cross-check the
+ * Hilbert-tiled kernel. */
+int chf_ham_apply_generic(chf_ham* ham, chf_dtype dtype, const void* X_dev, int64_t ldx, void* Y_dev,
+                          int64_t ldy, int nvec, void* stream);
+int chf_filter_generic(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
+                       double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
+
+/* k-step Lanczos (FP64) from v0_dev ([n_rows], padding zero): out3_host =
+ * {b = largest Ritz value + residual norm, smallest Ritz value, largest Ritz
+ * value}.  Upper bound of the spectrum used by the filter.  2 <= k <= 64. */
+int lanczos_bound(chf_ham* ham, chf_ctx* ctx, const double* v0_dev, int k, double* out3_host,
+                  void* stream);
+
+/* S = A^T B for row-major blocks A [n_rows][lda] (m columns) and B [n_rows][ldb]
+ * (n columns), accumulated on MFMA in the block precision; partial sums over
+ * row slices are added in FP64.  S_dev is FP64 row-major [m][lds].  With
+ * A == B and m == n only the upper triangle is computed and mirrored. */
+int gram(chf_ctx* ctx, chf_dtype dtype, const void* A_dev, int64_t lda, const void* B_dev,
+         int64_t ldb, int64_t n_rows, int m, int n, double* S_dev, int64_t lds, void* stream);
+
+/* Cholesky-QR (paper: the subspace orthonormalisation of ChFSI):
+ * S = X^T X (gram), S = R^T R in FP64, X <- X R^{-1} (the update in the block
+ * precision).  On breakdown in FP32 the Gram is recomputed with the
+ * vectors scaled by 1/norm and retried once (counted in *fallbacks, may be
+ * NULL); CHF_ENOTPD if that fails too. */
+int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int64_t n_rows, int nvec,
+                   int* fallbacks, void* stream);
+
+/* Rayleigh-Ritz (paper: the CheFSI paragraph): W = H X blockwise into work
+ * ([n_rows][ldw], ldw >= min(nvec, 256)), Hs = X^T W symmetrised (FP64),
+ * Hs = Q diag(eig) Q^T (FP64), X <- X Q.  eig_host [nvec] ascending. */
+int rayleigh_ritz(chf_ham* ham, chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec,
+                  double* eig_host, void* work_dev, int64_t ldw, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * SCF pieces (paper: Kohn-Sham DFT with LDA in the Perdew-Zunger form, SRE
+ * convergence criterion, the 4-then-1 ChFSI schedule).  All FP64.
+ * ------------------------------------------------------------------------- */
+
+/* rho[row] = sum_{i < n_occ} 2 X[row][i]^2 / h^3 (closed shell). */
+int chf_density(chf_ham* ham, chf_dtype dtype, const void* X_dev, int64_t ldx, int n_occ,
+                double* rho_dev, void* stream);
+
+/* Hartree potential: -L V = 4 pi rho on the inside points with the same
+ * 12th-order stencil; stencil points outside the sphere take the l <= 4
+ * multipole expansion of rho about the origin.  CG warm-started from vh_dev,
+ * stops at ||r|| / ||b|| < rtol; *iters_host (may be NULL) receives the count.
+ * CHF_ENOTCONV after max_iter iterations. */
+int chf_hartree(chf_ham* ham, chf_ctx* ctx, const double* rho_dev, double* vh_dev, double rtol,
+                int max_iter, int* iters_host, void* stream);
+
+/* PZ81 unpolarised LDA: eps_xc and v_xc per row (0 where rho < 1e-14). */
+int chf_lda(chf_ham* ham, const double* rho_dev, double* exc_dev, double* vxc_dev, void* stream);
+
+typedef struct {
+    int n_electrons;      /* closed shell: n_electrons / 2 occupied states            */
+    int nvec;             /* states tracked (columns of X)                            */
+    int degree;           /* Chebyshev degree                                         */
+    int first_iters;      /* ChFSI iterations in the first SCF step (paper: 4)        */
+    int later_iters;      /* ChFSI iterations in each later step (paper: 1)           */
+    int lanczos_k;        /* Lanczos steps for the upper bound                        */
+    int filter_dtype;     /* chf_dtype of the filter (H X recurrences)               */
+    int gram_dtype;       /* chf_dtype of the Gram products and X updates             */
+    int mix_history;      /* Anderson history length                                  */
+    double mix_beta;      /* Anderson mixing parameter                                */
+    double cg_rtol;       /* Poisson CG relative tolerance                            */
+    double e_ion;         /* ion-ion energy sum_{a<b} Z_a Z_b / R_ab (Ha)             */
+} chf_scf_params;
+
+typedef struct {
+    int step;             /* 1-based SCF step just completed                         */
+    int chfsi_iters;      /* ChFSI iterations done in it                             */
+    int cg_iters;         /* Poisson CG iterations (both solves)                     */
+    int chol_fallbacks;   /* Cholesky-QR fallbacks taken                             */
+    double sre_ry;        /* self-consistent residual error (Ry)                     */
+    double energy;        /* Harris-Foulkes total energy at rho_in (Ha)              */
+    double band_energy;   /* sum f_i eps_i (Ha)                                      */
+    double homo, lumo;    /* Ha                                                      */
+    double bound_a, bound_b, bound_a0;  /* filter bounds used in the last iteration  */
+} chf_scf_report;
+
+/* SCF state: owns rho_in, V_H, the Anderson history and the filter bounds;
+ * X and the work block stay caller-owned.  rho0_dev ([n_rows]) is the
+ * initial density, v_lanczos_dev ([n_rows]) the fixed Lanczos start vector. */
+int chf_scf_create(chf_ham* ham, chf_ctx* ctx, const chf_scf_params* params, const double* rho0_dev,
+                   const double* v_lanczos_dev, chf_scf** out);
+int chf_scf_destroy(chf_scf* scf);
+
+/* One SCF step: V_eff from rho_in, Lanczos bound, ChFSI iterations on X
+ * (filter, Cholesky-QR, Rayleigh-Ritz), rho_out, SRE, Harris-Foulkes energy,
+ * Anderson mixing of rho_in.  eig_host (may be NULL) receives the nvec Ritz
+ * values.  X: [n_rows][ldx] in filter_dtype; work: [n_rows][ldw], ldw >= nvec. */
+int scf_step(chf_scf* scf, void* X_dev, int64_t ldx, void* work_dev, int64_t ldw,
+             chf_scf_report* report, double* eig_host);
+
+/* Checkpoint access: copy rho_in / V_H ([n_rows] FP64) out of or into the
+ * state (device to device, on the SCF's stream). */
+int chf_scf_get_fields(chf_scf* scf, double* rho_in_dev, double* vh_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHFSI_H */

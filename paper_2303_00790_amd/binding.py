@@ -1,0 +1,338 @@
+"""ctypes binding of libchfsi.so: argument marshalling only.
+
+Every computation happens inside the HIP library; PyTorch only provides
+device memory (tensors) and the current HIP stream.  If the library has not
+been built this module raises on first use -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchfsi.so")
+
+CHF_F32, CHF_F64 = 1, 2
+ORDER_HILBERT, ORDER_LEX = 0, 1
+STATUS = {0: "CHF_OK", -1: "CHF_EINVAL", -2: "CHF_ENOMEM", -3: "CHF_EHIP", -4: "CHF_ENOTPD",
+          -5: "CHF_ENOTCONV", -6: "CHF_ENONFINITE", -7: "CHF_EUNSUPPORTED"}
+
+
+class ChfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("h", C.c_double), ("radius", C.c_double), ("ordering", C.c_int), ("keep_nbr", C.c_int),
+                ("dtypes", C.c_int)]
+
+
+class Atoms(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("pos_host", C.POINTER(C.c_double)), ("species_host", C.POINTER(C.c_int))]
+
+
+class PP(C.Structure):
+    _fields_ = [("z_si", C.c_double), ("z_h", C.c_double), ("r_loc_si", C.c_double), ("r_loc_h", C.c_double),
+                ("r_c", C.c_double), ("r_cut", C.c_double), ("h_s", C.c_double), ("h_p", C.c_double)]
+
+
+class ScfParams(C.Structure):
+    _fields_ = [("n_electrons", C.c_int), ("nvec", C.c_int), ("degree", C.c_int), ("first_iters", C.c_int),
+                ("later_iters", C.c_int), ("lanczos_k", C.c_int), ("filter_dtype", C.c_int),
+                ("gram_dtype", C.c_int), ("mix_history", C.c_int), ("mix_beta", C.c_double),
+                ("cg_rtol", C.c_double), ("e_ion", C.c_double)]
+
+
+class ScfReport(C.Structure):
+    _fields_ = [("step", C.c_int), ("chfsi_iters", C.c_int), ("cg_iters", C.c_int), ("chol_fallbacks", C.c_int),
+                ("sre_ry", C.c_double), ("energy", C.c_double), ("band_energy", C.c_double),
+                ("homo", C.c_double), ("lumo", C.c_double), ("bound_a", C.c_double), ("bound_b", C.c_double),
+                ("bound_a0", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+P = C.c_void_p
+I64 = C.c_int64
+D = C.c_double
+INT = C.c_int
+
+# name -> argtypes (all return int status except chf_last_error)
+_SIGS = {
+    "chf_ctx_create": [INT, C.POINTER(P)],
+    "chf_ctx_destroy": [P],
+    "ham_build": [C.POINTER(GridDesc), C.POINTER(Atoms), C.POINTER(PP), P, C.POINTER(P)],
+    "chf_ordering_host": [C.POINTER(GridDesc), C.POINTER(I64), C.POINTER(I64), P, P, P],
+    "chf_projectors_host": [C.POINTER(GridDesc), C.POINTER(Atoms), C.POINTER(PP), C.POINTER(I64), P, P, P],
+    "ham_destroy": [P],
+    "ham_info": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
+    "ham_export_ordering": [P, P, P, P],
+    "ham_get_vloc": [P, P, P],
+    "ham_set_veff": [P, P, P],
+    "ham_apply": [P, INT, P, I64, P, I64, INT, P],
+    "chf_ham_apply_generic": [P, INT, P, I64, P, I64, INT, P],
+    "chebyshev_filter": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
+    "chf_filter_generic": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
+    "lanczos_bound": [P, P, P, INT, P, P],
+    "gram": [P, INT, P, I64, P, I64, I64, INT, INT, P, I64, P],
+    "orthonormalize": [P, INT, P, I64, I64, INT, P, P],
+    "rayleigh_ritz": [P, P, INT, P, I64, INT, P, P, I64, P],
+    "chf_density": [P, INT, P, I64, INT, P, P],
+    "chf_hartree": [P, P, P, P, D, INT, P, P],
+    "chf_lda": [P, P, P, P, P],
+    "chf_scf_create": [P, P, C.POINTER(ScfParams), P, P, C.POINTER(P)],
+    "chf_scf_destroy": [P],
+    "scf_step": [P, P, I64, P, I64, C.POINTER(ScfReport), P],
+    "chf_scf_get_fields": [P, P, P],
+}
+
+_lib = None
+
+
+def lib():
+    """Load libchfsi.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        L.chf_last_error.restype = C.c_char_p
+        L.chf_last_error.argtypes = []
+        for name, args in _SIGS.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype = C.c_int
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    return ["chf_last_error", *_SIGS.keys()]
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise ChfError(rc, lib().chf_last_error().decode())
+
+
+def call(name: str, *args) -> None:
+    check(getattr(lib(), name)(*args))
+
+
+# ---------------------------------------------------------------------------
+# tensor helpers (torch imported lazily so host-only use needs no GPU)
+# ---------------------------------------------------------------------------
+def _stream():
+    import torch
+    return P(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> P:
+    return P(t.data_ptr())
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return CHF_F64
+    if t.dtype == torch.float32:
+        return CHF_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _block(t):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("vector blocks must be 2-D with contiguous rows")
+    return _ptr(t), t.stride(0)
+
+
+def make_pp(pp) -> PP:
+    return PP(pp.z_si, pp.z_h, pp.r_loc, pp.r_loc_h, pp.r_c, pp.r_cut, pp.h_s, pp.h_p)
+
+
+def _atoms(pos: np.ndarray, species: np.ndarray):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    species = np.ascontiguousarray(species, dtype=np.int32)
+    a = Atoms(len(species), pos.ctypes.data_as(C.POINTER(C.c_double)), species.ctypes.data_as(C.POINTER(C.c_int)))
+    return a, (pos, species)
+
+
+def ordering_host(h: float, radius: float, ordering: int = ORDER_HILBERT, with_nbr: bool = True):
+    g = GridDesc(h, radius, ordering, 0, 3)
+    n, nr = I64(), I64()
+    call("chf_ordering_host", C.byref(g), C.byref(n), C.byref(nr), None, None, None)
+    ijk = np.zeros((n.value, 3), np.int32)
+    rows = np.zeros(n.value, np.int64)
+    nbr = np.zeros((n.value, 36), np.int32) if with_nbr else None
+    call("chf_ordering_host", C.byref(g), C.byref(n), C.byref(nr), P(ijk.ctypes.data), P(rows.ctypes.data),
+         P(nbr.ctypes.data) if with_nbr else None)
+    return ijk, rows, nbr, nr.value
+
+
+def projectors_host(h: float, radius: float, pos, species, pp, ordering: int = ORDER_HILBERT):
+    g = GridDesc(h, radius, ordering, 0, 3)
+    a, keep = _atoms(pos, species)
+    cp = make_pp(pp)
+    npairs = I64()
+    call("chf_projectors_host", C.byref(g), C.byref(a), C.byref(cp), C.byref(npairs), None, None, None)
+    n_si = int((np.asarray(species) == 0).sum())
+    off = np.zeros(n_si + 1, np.int64)
+    rk = np.zeros(npairs.value, np.int32)
+    beta = np.zeros((npairs.value, 4), np.float64)
+    call("chf_projectors_host", C.byref(g), C.byref(a), C.byref(cp), C.byref(npairs), P(off.ctypes.data),
+         P(rk.ctypes.data), P(beta.ctypes.data))
+    return off, rk, beta
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.handle = P()
+        call("chf_ctx_create", device, C.byref(self.handle))
+
+    def close(self):
+        if self.handle:
+            call("chf_ctx_destroy", self.handle)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    """Device Hamiltonian handle (ham_build / ham_* calls)."""
+
+    def __init__(self, pos, species, pp, h: float, radius: float, ordering: int = ORDER_HILBERT,
+                 keep_nbr: bool = False, dtypes: int = 3):
+        g = GridDesc(h, radius, ordering, int(keep_nbr), dtypes)
+        a, keep = _atoms(pos, species)
+        cp = make_pp(pp)
+        self.handle = P()
+        call("ham_build", C.byref(g), C.byref(a), C.byref(cp), _stream(), C.byref(self.handle))
+        vals = [I64() for _ in range(5)]
+        call("ham_info", self.handle, *[C.byref(v) for v in vals])
+        self.n_points, self.n_rows, self.n_blocks, self.n_proj, self.n_pairs = [v.value for v in vals]
+        self.h = h
+        self.ordering = ordering
+
+    def close(self):
+        if self.handle:
+            call("ham_destroy", self.handle)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export_ordering(self, with_nbr: bool = False):
+        ijk = np.zeros((self.n_points, 3), np.int32)
+        rows = np.zeros(self.n_points, np.int64)
+        nbr = np.zeros((self.n_points, 36), np.int32) if with_nbr else None
+        call("ham_export_ordering", self.handle, P(ijk.ctypes.data), P(rows.ctypes.data),
+             P(nbr.ctypes.data) if with_nbr else None)
+        return ijk, rows, nbr
+
+    def vloc(self):
+        import torch
+        out = torch.empty(self.n_rows, dtype=torch.float64, device="cuda")
+        call("ham_get_vloc", self.handle, _ptr(out), _stream())
+        return out
+
+    def set_veff(self, veff):
+        call("ham_set_veff", self.handle, _ptr(veff.contiguous()), _stream())
+
+    def apply(self, X, Y, generic: bool = False):
+        px, ldx = _block(X)
+        py, ldy = _block(Y)
+        call("chf_ham_apply_generic" if generic else "ham_apply", self.handle, _dtype_code(X), px, ldx, py, ldy,
+             X.shape[1], _stream())
+
+    def filter(self, X, work, degree: int, a: float, b: float, a0: float, generic: bool = False, nvec=None):
+        px, ldx = _block(X)
+        pw, ldw = _block(work)
+        call("chf_filter_generic" if generic else "chebyshev_filter", self.handle, _dtype_code(X), px, ldx,
+             nvec or X.shape[1], degree, a, b, a0, pw, ldw, _stream())
+
+    def lanczos_bound(self, ctx: Context, v0, k: int = 10):
+        out = (C.c_double * 3)()
+        call("lanczos_bound", self.handle, ctx.handle, _ptr(v0), k, C.cast(out, P), _stream())
+        return tuple(out)
+
+    def density(self, X, n_occ: int, rho):
+        px, ldx = _block(X)
+        call("chf_density", self.handle, _dtype_code(X), px, ldx, n_occ, _ptr(rho), _stream())
+
+    def hartree(self, ctx: Context, rho, vh, rtol: float = 1e-12, max_iter: int = 20000) -> int:
+        it = C.c_int()
+        call("chf_hartree", self.handle, ctx.handle, _ptr(rho), _ptr(vh), rtol, max_iter, C.byref(it), _stream())
+        return it.value
+
+    def lda(self, rho, exc, vxc):
+        call("chf_lda", self.handle, _ptr(rho), _ptr(exc), _ptr(vxc), _stream())
+
+
+def gram(ctx: Context, A, B, S) -> None:
+    pa, lda = _block(A)
+    pb, ldb = _block(B)
+    ps, lds = _block(S)
+    call("gram", ctx.handle, _dtype_code(A), pa, lda, pb, ldb, A.shape[0], A.shape[1], B.shape[1], ps, lds, _stream())
+
+
+def orthonormalize(ctx: Context, X, nvec=None) -> int:
+    px, ldx = _block(X)
+    fb = C.c_int()
+    call("orthonormalize", ctx.handle, _dtype_code(X), px, ldx, X.shape[0], nvec or X.shape[1], C.byref(fb), _stream())
+    return fb.value
+
+
+def rayleigh_ritz(H: Hamiltonian, ctx: Context, X, work, nvec=None) -> np.ndarray:
+    px, ldx = _block(X)
+    pw, ldw = _block(work)
+    n = nvec or X.shape[1]
+    eig = np.zeros(n, np.float64)
+    call("rayleigh_ritz", H.handle, ctx.handle, _dtype_code(X), px, ldx, n, P(eig.ctypes.data), pw, ldw, _stream())
+    return eig
+
+
+class Scf:
+    """SCF state handle (chf_scf_create / scf_step)."""
+
+    def __init__(self, H: Hamiltonian, ctx: Context, params: ScfParams, rho0, v_lanczos):
+        self.handle = P()
+        self._keep = (H, ctx)
+        call("chf_scf_create", H.handle, ctx.handle, C.byref(params), _ptr(rho0), _ptr(v_lanczos),
+             C.byref(self.handle))
+        self.nvec = params.nvec
+
+    def step(self, X, work):
+        px, ldx = _block(X)
+        pw, ldw = _block(work)
+        rep = ScfReport()
+        eig = np.zeros(self.nvec, np.float64)
+        call("scf_step", self.handle, px, ldx, pw, ldw, C.byref(rep), P(eig.ctypes.data))
+        return rep, eig
+
+    def fields(self, rho_in, vh):
+        call("chf_scf_get_fields", self.handle, _ptr(rho_in), _ptr(vh))
+
+    def close(self):
+        if self.handle:
+            call("chf_scf_destroy", self.handle)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,397 @@
+// C ABI: handles, argument validation, error model, and the Hamiltonian /
+// filter entry points.  Every entry point catches everything and returns a
+// status code; chf_last_error() holds the message.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <type_traits>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace chf {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+void fail(int code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error(code, buf);
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        return CHF_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return CHF_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return CHF_EHIP;
+    } catch (...) {
+        set_last_error("unknown error");
+        return CHF_EHIP;
+    }
+}
+
+// The FD weights c_k of the central 2p-order second derivative (p = 6), from
+// the closed form c_k = 2 (-1)^(k+1) (p!)^2 / (k^2 (p-k)! (p+k)!), c_0 = -2 sum c_k.
+static void fd_weights(double c[7]) {
+    const int p = kHalf;
+    auto fact = [](int n) {
+        double f = 1;
+        for (int i = 2; i <= n; ++i) f *= i;
+        return f;
+    };
+    double s = 0;
+    for (int k = 1; k <= p; ++k) {
+        c[k] = 2.0 * ((k + 1) % 2 ? -1.0 : 1.0) * fact(p) * fact(p) / (double(k) * k * fact(p - k) * fact(p + k));
+        s += c[k];
+    }
+    c[0] = -2.0 * s;
+}
+
+template <class T>
+static std::vector<T> cast_scaled(const std::vector<double>& v, const double scale[4]) {
+    std::vector<T> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = T(v[i] * scale[i % 4]);
+    return out;
+}
+
+static void check_device(const chf_ham* H) {
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    CHF_REQUIRE(dev == H->device, "handle belongs to device %d, current device is %d", H->device, dev);
+}
+
+static size_t dsize(int dtype) { return dtype == CHF_F64 ? 8 : 4; }
+
+static void check_block(const chf_ham* H, int dtype, const void* p, int64_t ld, int nvec, const char* what) {
+    CHF_REQUIRE(dtype == CHF_F32 || dtype == CHF_F64, "%s: dtype must be CHF_F32 or CHF_F64", what);
+    CHF_REQUIRE(H->dtypes & (dtype == CHF_F64 ? 2 : 1), "%s: the handle was not built for this dtype", what);
+    CHF_REQUIRE(p != nullptr, "%s: null block", what);
+    CHF_REQUIRE(nvec >= 1, "%s: nvec must be >= 1", what);
+    CHF_REQUIRE(ld >= nvec, "%s: ld (%lld) < nvec (%d)", what, (long long)ld, nvec);
+    (void)H;
+}
+
+}  // namespace chf
+
+namespace chf {
+// Degree-m scaled filter.  With e = (b - a) / 2, c = (b + a) / 2 and
+// sigma_k = T_{k-1}(t0) / T_k(t0), t0 = (a0 - c) / e, the normalised
+// iterates Y_k = T_k((H - c) / e) X / T_k(t0) obey
+//   Y_1 = (sigma_1 / e) (H - c) X,
+//   Y_k = (2 sigma_k / e) (H - c) Y_{k-1} - sigma_{k-1} sigma_k Y_{k-2},
+//   sigma_1 = e / (a0 - c), sigma_k = 1 / (2 / sigma_1 - sigma_{k-1}).
+// Y_k overwrites Y_{k-2} in place (X for even k, work for odd k).
+template <class T>
+static void run_filter(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b, double a0,
+                       hipStream_t s, int force_kernel) {
+    const double e = (b - a) / 2, c = (b + a) / 2;
+    const double sigma1 = e / (a0 - c);
+    double sigma = sigma1;
+    hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, nvec, sigma1 / e, c, 0.0, s, force_kernel);
+    for (int k = 2; k <= m; ++k) {
+        const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
+        const double alpha = 2.0 * sigma_next / e, beta = sigma * sigma_next;
+        if (k % 2 == 0)
+            hx_step<T>(H, W, ldw, X, ldx, X, ldx, nvec, alpha, c, beta, s, force_kernel);
+        else
+            hx_step<T>(H, X, ldx, W, ldw, W, ldw, nvec, alpha, c, beta, s, force_kernel);
+        sigma = sigma_next;
+    }
+    if (m % 2 == 1)
+        HIP_CHECK(hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), W, size_t(ldw) * sizeof(T), size_t(nvec) * sizeof(T),
+                                   size_t(H->grid.n_rows), hipMemcpyDeviceToDevice, s));
+}
+
+static int filter_impl(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
+                       double a0, void* work, int64_t ldw, void* stream, int force_kernel) {
+    return guarded([&] {
+        CHF_REQUIRE(H, "chebyshev_filter: null handle");
+        check_device(H);
+        check_block(H, dtype, X, ldx, nvec, "chebyshev_filter X");
+        check_block(H, dtype, work, ldw, nvec, "chebyshev_filter work");
+        CHF_REQUIRE(degree >= 1 && degree <= 1000, "chebyshev_filter: degree must be in [1, 1000]");
+        CHF_REQUIRE(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0), "chebyshev_filter: non-finite bounds");
+        CHF_REQUIRE(a < b && a0 < a, "chebyshev_filter: need a0 < a < b");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (dtype == CHF_F64)
+            run_filter<double>(H, static_cast<double*>(X), ldx, static_cast<double*>(work), ldw, nvec, degree, a, b, a0, s,
+                               force_kernel);
+        else
+            run_filter<float>(H, static_cast<float*>(X), ldx, static_cast<float*>(work), ldw, nvec, degree, a, b, a0, s,
+                              force_kernel);
+    });
+}
+
+}  // namespace chf
+
+using namespace chf;
+
+extern "C" {
+
+const char* chf_last_error(void) { return g_last_error.c_str(); }
+
+int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp, void* stream, chf_ham** out) {
+    return guarded([&] {
+        CHF_REQUIRE(gd && atoms && pp && out, "ham_build: null argument");
+        *out = nullptr;
+        CHF_REQUIRE(gd->h > 0 && std::isfinite(gd->h), "ham_build: h must be positive");
+        CHF_REQUIRE(gd->radius > gd->h && std::isfinite(gd->radius), "ham_build: radius must exceed h");
+        CHF_REQUIRE(gd->ordering == CHF_ORDER_HILBERT || gd->ordering == CHF_ORDER_LEX, "ham_build: bad ordering");
+        CHF_REQUIRE(gd->dtypes >= 1 && gd->dtypes <= 3, "ham_build: dtypes mask must be 1, 2 or 3");
+        CHF_REQUIRE(gd->radius / gd->h < 4000.0, "ham_build: grid too large");
+        CHF_REQUIRE(atoms->n_atoms >= 0 && (atoms->n_atoms == 0 || (atoms->pos_host && atoms->species_host)),
+                    "ham_build: bad atom list");
+        for (int a = 0; a < atoms->n_atoms; ++a) {
+            CHF_REQUIRE(atoms->species_host[a] == 0 || atoms->species_host[a] == 1, "ham_build: species must be 0 or 1");
+            for (int d = 0; d < 3; ++d) CHF_REQUIRE(std::isfinite(atoms->pos_host[3 * a + d]), "ham_build: non-finite position");
+        }
+        CHF_REQUIRE(pp->r_c > 0 && pp->r_cut > 0 && pp->r_loc_si > 0 && pp->r_loc_h > 0, "ham_build: bad pseudopotential");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        auto H = std::make_unique<chf_ham>();
+        HIP_CHECK(hipGetDevice(&H->device));
+        H->h = gd->h;
+        H->dtypes = gd->dtypes;
+        H->stream = s;
+        double c[7];
+        fd_weights(c);
+        for (int k = 0; k < 7; ++k) H->coef[k] = -0.5 * c[k] / (gd->h * gd->h);
+        HostGrid& g = H->grid;
+        build_grid(g, gd->h, gd->radius, gd->ordering);
+        CHF_REQUIRE(g.n_rows < (int64_t(1) << 31), "ham_build: more than 2^31 rows");
+        // per-row coordinates and inside flags
+        {
+            std::vector<int32_t> ijk4(size_t(g.n_rows) * 4, 0);
+            std::vector<uint8_t> inside(size_t(g.n_rows), 0);
+            for (int64_t p = 0; p < g.n; ++p) {
+                const int64_t r = g.row_of_rank[size_t(p)];
+                for (int d = 0; d < 3; ++d) ijk4[size_t(4 * r + d)] = g.ijk[size_t(3 * p + d)];
+                ijk4[size_t(4 * r + 3)] = 1;
+                inside[size_t(r)] = 1;
+            }
+            upload(H->row_ijk4, ijk4, s);
+            upload(H->row_inside, inside, s);
+        }
+        if (gd->ordering == CHF_ORDER_HILBERT) {
+            upload(H->block_nbr, g.block_nbr, s);
+            upload(H->block_mask, g.block_mask, s);
+        }
+        if (gd->keep_nbr || gd->ordering == CHF_ORDER_LEX) {
+            std::vector<int32_t> nbr;
+            build_row_neighbours(g, nbr);
+            upload(H->nbr_rows, nbr, s);
+            H->has_nbr = true;
+        }
+        // projectors
+        build_projectors(g, *atoms, *pp, H->proj);
+        const HostProj& P = H->proj;
+        upload(H->sup_off, P.sup_off, s);
+        upload(H->sup_row, P.sup_row, s);
+        upload(H->ent_off, P.ent_off, s);
+        upload(H->ent_atom, P.ent_atom, s);
+        const double h3 = gd->h * gd->h * gd->h;
+        const double gsc[4] = {h3, h3, h3, h3};
+        const double ssc[4] = {pp->h_s, pp->h_p, pp->h_p, pp->h_p};
+        if (gd->dtypes & 2) {
+            upload(H->sup_beta64, cast_scaled<double>(P.sup_beta, gsc), s);
+            upload(H->ent_beta64, cast_scaled<double>(P.ent_beta, ssc), s);
+        }
+        if (gd->dtypes & 1) {
+            upload(H->sup_beta32, cast_scaled<float>(P.sup_beta, gsc), s);
+            upload(H->ent_beta32, cast_scaled<float>(P.ent_beta, ssc), s);
+        }
+        // local potential (FP64, all atoms)
+        H->vloc.alloc(size_t(g.n_rows) * 8);
+        if (gd->dtypes & 2) H->veff64.alloc(size_t(g.n_rows) * 8);
+        if (gd->dtypes & 1) H->veff32.alloc(size_t(g.n_rows) * 4);
+        {
+            std::vector<double> at(size_t(std::max(1, atoms->n_atoms)) * 4, 0.0), wd(size_t(std::max(1, atoms->n_atoms)), 1.0);
+            for (int a = 0; a < atoms->n_atoms; ++a) {
+                for (int d = 0; d < 3; ++d) at[size_t(4 * a + d)] = atoms->pos_host[3 * a + d];
+                const bool si = atoms->species_host[a] == 0;
+                at[size_t(4 * a + 3)] = si ? pp->z_si : pp->z_h;
+                wd[size_t(a)] = si ? pp->r_loc_si : pp->r_loc_h;
+            }
+            DevBuf dat, dwd, bad;
+            upload(dat, at, s);
+            upload(dwd, wd, s);
+            launch_vloc(H.get(), dat.as<double4>(), dwd.as<double>(), atoms->n_atoms, s);
+            bad.alloc(sizeof(int));
+            HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+            launch_cast_veff(H.get(), H->vloc.as<double>(), H->veff64.as<double>(), H->veff32.as<float>(), bad.as<int>(), s);
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
+        *out = H.release();
+    });
+}
+
+int chf_ordering_host(const chf_grid_desc* gd, int64_t* n_points, int64_t* n_rows, int32_t* ijk_host,
+                      int64_t* row_of_rank_host, int32_t* nbr_host) {
+    return guarded([&] {
+        CHF_REQUIRE(gd && n_points && n_rows, "chf_ordering_host: null argument");
+        CHF_REQUIRE(gd->h > 0 && gd->radius > gd->h && gd->radius / gd->h < 4000.0, "chf_ordering_host: bad grid");
+        CHF_REQUIRE(gd->ordering == CHF_ORDER_HILBERT || gd->ordering == CHF_ORDER_LEX, "chf_ordering_host: bad ordering");
+        HostGrid g;
+        build_grid(g, gd->h, gd->radius, gd->ordering);
+        *n_points = g.n;
+        *n_rows = g.n_rows;
+        if (ijk_host) std::memcpy(ijk_host, g.ijk.data(), g.ijk.size() * sizeof(int32_t));
+        if (row_of_rank_host) std::memcpy(row_of_rank_host, g.row_of_rank.data(), g.row_of_rank.size() * sizeof(int64_t));
+        if (nbr_host) {
+            std::vector<int32_t> rows;
+            build_row_neighbours(g, rows);
+            for (int64_t p = 0; p < g.n; ++p) {
+                const int32_t* src = &rows[size_t(g.row_of_rank[size_t(p)]) * kNbr];
+                for (int c = 0; c < kNbr; ++c) nbr_host[p * kNbr + c] = src[c] < 0 ? -1 : g.rank_of_row[size_t(src[c])];
+            }
+        }
+    });
+}
+
+int chf_projectors_host(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp, int64_t* n_pairs,
+                        int64_t* sup_off_host, int32_t* sup_rank_host, double* sup_beta_host) {
+    return guarded([&] {
+        CHF_REQUIRE(gd && atoms && pp && n_pairs, "chf_projectors_host: null argument");
+        CHF_REQUIRE(gd->h > 0 && gd->radius > gd->h && gd->radius / gd->h < 4000.0, "chf_projectors_host: bad grid");
+        HostGrid g;
+        build_grid(g, gd->h, gd->radius, gd->ordering);
+        HostProj P;
+        build_projectors(g, *atoms, *pp, P);
+        *n_pairs = int64_t(P.sup_row.size());
+        if (sup_off_host) std::memcpy(sup_off_host, P.sup_off.data(), P.sup_off.size() * sizeof(int64_t));
+        if (sup_rank_host)
+            for (size_t j = 0; j < P.sup_row.size(); ++j) sup_rank_host[j] = g.rank_of_row[size_t(P.sup_row[j])];
+        if (sup_beta_host) std::memcpy(sup_beta_host, P.sup_beta.data(), P.sup_beta.size() * sizeof(double));
+    });
+}
+
+int ham_destroy(chf_ham* H) {
+    return guarded([&] {
+        if (!H) return;
+        (void)hipDeviceSynchronize();
+        delete H;
+    });
+}
+
+int ham_info(const chf_ham* H, int64_t* n_points, int64_t* n_rows, int64_t* n_blocks, int64_t* n_proj,
+             int64_t* n_pairs) {
+    return guarded([&] {
+        CHF_REQUIRE(H, "ham_info: null handle");
+        if (n_points) *n_points = H->grid.n;
+        if (n_rows) *n_rows = H->grid.n_rows;
+        if (n_blocks) *n_blocks = H->grid.n_blocks;
+        if (n_proj) *n_proj = H->proj.n_proj;
+        if (n_pairs) *n_pairs = int64_t(H->proj.sup_row.size());
+    });
+}
+
+int ham_export_ordering(const chf_ham* H, int32_t* ijk, int64_t* row_of_rank, int32_t* nbr) {
+    return guarded([&] {
+        CHF_REQUIRE(H, "ham_export_ordering: null handle");
+        const HostGrid& g = H->grid;
+        if (ijk) std::memcpy(ijk, g.ijk.data(), g.ijk.size() * sizeof(int32_t));
+        if (row_of_rank) std::memcpy(row_of_rank, g.row_of_rank.data(), g.row_of_rank.size() * sizeof(int64_t));
+        if (nbr) {
+            std::vector<int32_t> rows;
+            build_row_neighbours(g, rows);
+            for (int64_t p = 0; p < g.n; ++p) {
+                const int32_t* src = &rows[size_t(g.row_of_rank[size_t(p)]) * kNbr];
+                for (int c = 0; c < kNbr; ++c) nbr[p * kNbr + c] = src[c] < 0 ? -1 : g.rank_of_row[size_t(src[c])];
+            }
+        }
+    });
+}
+
+int ham_get_vloc(const chf_ham* H, double* vloc_dev, void* stream) {
+    return guarded([&] {
+        CHF_REQUIRE(H && vloc_dev, "ham_get_vloc: null argument");
+        check_device(H);
+        HIP_CHECK(hipMemcpyAsync(vloc_dev, H->vloc.p, size_t(H->grid.n_rows) * 8, hipMemcpyDeviceToDevice,
+                                 static_cast<hipStream_t>(stream)));
+    });
+}
+
+int ham_set_veff(chf_ham* H, const double* veff_dev, void* stream) {
+    return guarded([&] {
+        CHF_REQUIRE(H && veff_dev, "ham_set_veff: null argument");
+        check_device(H);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf bad;
+        bad.alloc(sizeof(int));
+        HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        // validate first (no writes), then cast
+        launch_cast_veff(H, veff_dev, nullptr, nullptr, bad.as<int>(), s);
+        int hbad = 0;
+        HIP_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (hbad) fail(CHF_ENONFINITE, "ham_set_veff: NaN or Inf in V_eff");
+        launch_cast_veff(H, veff_dev, H->veff64.as<double>(), H->veff32.as<float>(), bad.as<int>(), s);
+    });
+}
+
+int ham_apply(chf_ham* H, chf_dtype dtype, const void* X, int64_t ldx, void* Y, int64_t ldy, int nvec, void* stream) {
+    return guarded([&] {
+        CHF_REQUIRE(H, "ham_apply: null handle");
+        check_device(H);
+        check_block(H, dtype, X, ldx, nvec, "ham_apply X");
+        check_block(H, dtype, Y, ldy, nvec, "ham_apply Y");
+        const size_t es = dsize(dtype);
+        const char* xb = static_cast<const char*>(X);
+        const char* yb = static_cast<const char*>(Y);
+        const size_t span_x = size_t(H->grid.n_rows) * size_t(ldx) * es, span_y = size_t(H->grid.n_rows) * size_t(ldy) * es;
+        CHF_REQUIRE(xb + span_x <= yb || yb + span_y <= xb, "ham_apply: X and Y overlap");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (dtype == CHF_F64)
+            hx_step<double>(H, static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, nullptr, 0, nvec, 1.0, 0.0,
+                            0.0, s, 0);
+        else
+            hx_step<float>(H, static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, nullptr, 0, nvec, 1.0, 0.0,
+                           0.0, s, 0);
+    });
+}
+
+int chebyshev_filter(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
+                     double a0, void* work, int64_t ldw, void* stream) {
+    return filter_impl(H, dtype, X, ldx, nvec, degree, a, b, a0, work, ldw, stream, 0);
+}
+
+// Same filter forced onto the neighbour-table kernel (layout-independent
+// reference path on the device; needs keep_nbr).
+int chf_filter_generic(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
+                       double a0, void* work, int64_t ldw, void* stream) {
+    return filter_impl(H, dtype, X, ldx, nvec, degree, a, b, a0, work, ldw, stream, 1);
+}
+
+int chf_ham_apply_generic(chf_ham* H, chf_dtype dtype, const void* X, int64_t ldx, void* Y, int64_t ldy, int nvec,
+                          void* stream) {
+    return guarded([&] {
+        CHF_REQUIRE(H, "chf_ham_apply_generic: null handle");
+        check_device(H);
+        check_block(H, dtype, X, ldx, nvec, "apply X");
+        check_block(H, dtype, Y, ldy, nvec, "apply Y");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (dtype == CHF_F64)
+            hx_step<double>(H, static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, nullptr, 0, nvec, 1.0, 0.0,
+                            0.0, s, 1);
+        else
+            hx_step<float>(H, static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, nullptr, 0, nvec, 1.0, 0.0,
+                           0.0, s, 1);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+"""Host-side checks of the C-ABI library (no GPU): it loads, exports every
+symbol the header declares, and its host-built ordering, neighbour and
+projector tables equal the oracle's bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import grid as G
+from oracle import hamiltonian as OH
+from synth.cluster import make_cluster
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+B = pytest.importorskip("paper_2303_00790_amd.binding")
+
+if not os.path.exists(B.LIB_PATH):
+    pytest.skip("libchfsi.so not built", allow_module_level=True)
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "chfsi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _header_symbols()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares exactly the header's calls
+    assert sorted(B.declared_symbols()) == names
+
+
+def test_error_path_sets_message():
+    import ctypes
+    g = B.GridDesc(-1.0, 5.0, 0, 0, 3)
+    n, nr = ctypes.c_int64(), ctypes.c_int64()
+    rc = B.lib().chf_ordering_host(ctypes.byref(g), ctypes.byref(n), ctypes.byref(nr), None, None, None)
+    assert rc == -1 and b"bad grid" in B.lib().chf_last_error()
+
+
+@pytest.mark.parametrize("radius,h,ordering", [(18.0935, 0.7, G.ORDER_HILBERT), (18.0935, 0.7, G.ORDER_LEX),
+                                               (9.3, 0.45, G.ORDER_HILBERT), (5.61, 1.0, G.ORDER_HILBERT),
+                                               (12.0, 0.6, G.ORDER_LEX)])
+def test_ordering_bit_exact(radius, h, ordering):
+    ijk, rows, nbr, n_rows = B.ordering_host(h, radius, ordering)
+    g = G.build_grid(radius, h, ordering)
+    assert np.array_equal(ijk, g.ijk)
+    assert np.array_equal(rows, g.row_of_rank)
+    assert n_rows == g.n_rows
+    assert np.array_equal(nbr, G.neighbour_table(g))
+
+
+def test_ordering_random_radii():
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        h = float(rng.uniform(0.5, 1.0))
+        radius = float(rng.uniform(3.0, 12.0))
+        ijk, rows, _, n_rows = B.ordering_host(h, radius, G.ORDER_HILBERT, with_nbr=False)
+        g = G.build_grid(radius, h)
+        assert np.array_equal(ijk, g.ijk) and np.array_equal(rows, g.row_of_rank) and n_rows == g.n_rows
+
+
+def test_projector_tables_match_oracle():
+    c = make_cluster(5.5, 1001)
+    radius = c.domain_radius()
+    pp = OH.PseudoParams()
+    off, rank, beta = B.projectors_host(0.7, radius, c.pos, c.species, pp)
+    g = G.build_grid(radius, 0.7)
+    Bm, _ = OH.projector_matrix(g, c.pos, c.species, pp)
+    Bm = Bm.tocsc()
+    assert len(off) == Bm.shape[1] // 4 + 1
+    for a in range(len(off) - 1):
+        col = Bm[:, 4 * a:4 * a + 4].tocoo()
+        rows_o = np.unique(col.row)
+        assert np.array_equal(rank[off[a]:off[a + 1]], rows_o)
+        dense = Bm[rows_o, 4 * a:4 * a + 4].toarray()
+        assert np.allclose(beta[off[a]:off[a + 1]], dense, rtol=1e-14, atol=1e-17)
