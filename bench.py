@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Single-GPU throughput of the Chebyshev filter Y = p_m(H) X.
+
+One step = one chebyshev_filter call (degree m) over one block of vectors on
+the full grid of the workload's cluster (inputs resident in HBM).  Metric:
+filtered grid-point-vectors per second = N_points * n_vec / t_step.
+
+Printed as one JSON line, with the roofline of the dominant kernel (the
+Hilbert-tiled H X + recurrence kernel, timed with HIP events on its launch
+stream inside the library) and the oracle's rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="d16nm")
+    ap.add_argument("--dtype", default=None, choices=[None, "f32", "f64"])
+    ap.add_argument("--nvec", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="JSON with counter-derived HBM bytes per H X launch for this workload")
+    return ap.parse_args()
+
+
+def cpu_baseline(degree: int) -> dict:
+    """The FP64 oracle filter timed on the host on a bounded sample: the
+    0.55 nm cluster's full grid (72,455 points) with 128 vectors, same degree."""
+    import numpy as np
+    from oracle import chfsi as OC
+    from oracle import grid as OG
+    from oracle import hamiltonian as OH
+    from synth.cluster import make_cluster, random_block
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS["si35h36"]
+    c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
+    g = OG.build_grid(c.domain_radius(), wl.h)
+    Ho = OH.build_hamiltonian(g, c.pos, c.species, OH.PseudoParams())
+    nvec = 128
+    X = random_block(g.n, nvec, wl.x_seed)
+    b, tmin, _ = OC.lanczos_bound(Ho.apply, random_block(g.n, 1, wl.lanczos_seed)[:, 0])
+    a0 = float(Ho.veff.min())
+    a = tmin + 0.1 * (b - tmin)
+    t0 = time.perf_counter()
+    OC.chebyshev_filter(Ho.apply, X, degree, a, b, a0)
+    dt = time.perf_counter() - t0
+    return {"value": g.n * nvec / dt, "unit": "gridpt*vectors/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle degree-{degree} filter, 0.55 nm Si35H36 grid ({g.n} points) x {nvec} vectors "
+                      f"(scipy CSR SpMM, single-threaded), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              f"multi-GPU sharding is not provided", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2303_00790_amd import binding as B
+    from synth.cluster import make_cluster
+    from synth.workloads import MODEL_PP, WORKLOADS
+
+    wl = WORKLOADS[args.workload]
+    dtype_name = args.dtype or wl.dtype
+    tdtype = torch.float32 if dtype_name == "f32" else torch.float64
+    nvec = args.nvec or wl.nvec
+    es = 4 if dtype_name == "f32" else 8
+    torch.cuda.set_device(0)
+
+    t_setup = time.perf_counter()
+    c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
+    radius = c.domain_radius()
+    H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, B.ORDER_HILBERT, keep_nbr=False, dtypes=3)
+    _, rows_np, _ = H.export_ordering()
+    rows = torch.from_numpy(rows_np).cuda()
+    inside = torch.zeros(H.n_rows, dtype=torch.bool, device="cuda")
+    inside[rows] = True
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl.x_seed)
+    X = torch.randn((H.n_rows, nvec), generator=gen, dtype=tdtype, device="cuda")
+    X.mul_(inside[:, None])
+    W = torch.zeros_like(X)
+    gen.manual_seed(wl.lanczos_seed)
+    v0 = torch.randn(H.n_rows, generator=gen, dtype=torch.float64, device="cuda") * inside
+    ctx = B.Context(0)
+    b, tmin, _ = H.lanczos_bound(ctx, v0, 10)
+    vloc = H.vloc()
+    a0 = float(vloc[inside].min())           # rigorous lower bound: -1/2 L >= 0, KB energies >= 0
+    a = tmin + 0.1 * (b - tmin)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print(f"# setup {t_setup:.1f} s: {H.n_points} points, {H.n_rows} rows, {H.n_blocks} blocks, "
+          f"{H.n_proj} projector atoms, {H.n_pairs} pairs; bounds a0={a0:.4f} a={a:.4f} b={b:.4f}",
+          file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        H.filter(X, W, wl.degree, a, b, a0)
+    torch.cuda.synchronize()
+    B.timer(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        H.filter(X, W, wl.degree, a, b, a0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    tm = B.timer_read()
+    B.timer(False)
+    if not bool(torch.isfinite(X).all()):
+        print("bench.py: non-finite values in the filtered block", file=sys.stderr)
+        sys.exit(3)
+
+    n_pts = H.n_points
+    value = n_pts * nvec / (ms / 1e3)
+    # algorithmic bytes of the H X + recurrence launches: every launch reads Y_k
+    # and writes Y_{k+1}; all but the first of each filter pass also read Y_{k-1}
+    launches = tm["hx_launches"]
+    per_pass_bytes = n_pts * nvec * es * (2 + 3 * (wl.degree - 1))
+    alg_bytes_per_launch = per_pass_bytes / wl.degree
+    hx_avg_s = tm["hx_ms"] / 1e3 / max(1, launches)
+    achieved = alg_bytes_per_launch / hx_avg_s / 1e9
+    traffic = None
+    if os.path.exists(args.traffic):
+        rec = json.load(open(args.traffic)).get(f"{wl.name}:{dtype_name}:{nvec}")
+        if rec:
+            traffic = rec.get("bytes_per_launch")
+    out = {
+        "metric": "filtered gridpt*vectors/s (Chebyshev filter, one GPU)",
+        "value": value,
+        "unit": "gridpt*vectors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.description}", "points": n_pts, "rows": H.n_rows,
+                   "vectors": nvec, "degree": wl.degree, "projector_atoms": H.n_proj, "h_bohr": wl.h,
+                   "per_degree_rate": value * wl.degree},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "hx_tiled_kernel", "avg_launch_ms": hx_avg_s * 1e3,
+                     "alg_bytes_per_launch": alg_bytes_per_launch,
+                     "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"])},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl.degree)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,14 @@ int chf_ham_apply_generic(chf_ham* ham, chf_dtype dtype, const void* X_dev, int6
 int chf_filter_generic(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
                        double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
 
+/* Kernel timing (instrumentation): while enabled, HIP events are recorded on
+ * the launch stream around every H X launch (slot 0) and every KB-gather
+ * launch (slot 1).  chf_timer(1) clears and enables, chf_timer(0) disables;
+ * chf_timer_read synchronises the device and returns per slot the summed
+ * milliseconds (ms_host[2]) and the launch counts (launches_host[2]). */
+int chf_timer(int enable);
+int chf_timer_read(double* ms_host, int64_t* launches_host);
+
 /* k-step Lanczos (FP64) from v0_dev ([n_rows], padding zero): out3_host =
  * {b = largest Ritz value + residual norm, smallest Ritz value, largest Ritz
  * value}.  Upper bound of the spectrum used by the filter.  2 <= k <= 64. */
@@ -224,6 +232,15 @@ int chf_hartree(chf_ham* ham, chf_ctx* ctx, const double* rho_dev, double* vh_de
 
 /* PZ81 unpolarised LDA: eps_xc and v_xc per row (0 where rho < 1e-14). */
 int chf_lda(chf_ham* ham, const double* rho_dev, double* exc_dev, double* vxc_dev, void* stream);
+
+/* Initial density: superposition of Gaussian atoms Z (alpha / pi)^(3/2)
+ * exp(-alpha r^2) (Z = 4 for Si, 1 for H; exponents per species), rescaled so
+ * that h^3 sum rho = n_electrons.  rho_dev [n_rows] FP64 (padding 0). */
+int chf_sad_density(chf_ham* ham, const chf_atoms* atoms, double alpha_si, double alpha_h, int n_electrons,
+                    double* rho_dev, void* stream);
+
+/* Ion-ion energy sum_{a < b} Z_a Z_b / |R_a - R_b| (host, Ha). */
+int chf_ion_energy(const chf_atoms* atoms, const chf_pp* pp, double* out_host);
 
 typedef struct {
     int n_electrons;      /* closed shell: n_electrons / 2 occupied states            */

@@ -79,12 +79,16 @@ _SIGS = {
     "chebyshev_filter": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
     "chf_filter_generic": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
     "lanczos_bound": [P, P, P, INT, P, P],
+    "chf_timer": [INT],
+    "chf_timer_read": [P, P],
     "gram": [P, INT, P, I64, P, I64, I64, INT, INT, P, I64, P],
     "orthonormalize": [P, INT, P, I64, I64, INT, P, P],
     "rayleigh_ritz": [P, P, INT, P, I64, INT, P, P, I64, P],
     "chf_density": [P, INT, P, I64, INT, P, P],
     "chf_hartree": [P, P, P, P, D, INT, P, P],
     "chf_lda": [P, P, P, P, P],
+    "chf_sad_density": [P, C.POINTER(Atoms), D, D, INT, P, P],
+    "chf_ion_energy": [C.POINTER(Atoms), C.POINTER(PP), C.POINTER(D)],
     "chf_scf_create": [P, P, C.POINTER(ScfParams), P, P, C.POINTER(P)],
     "chf_scf_destroy": [P],
     "scf_step": [P, P, I64, P, I64, C.POINTER(ScfReport), P],
@@ -191,6 +195,17 @@ def projectors_host(h: float, radius: float, pos, species, pp, ordering: int = O
     return off, rk, beta
 
 
+def timer(enable: bool) -> None:
+    call("chf_timer", int(enable))
+
+
+def timer_read() -> dict:
+    ms = (C.c_double * 2)()
+    n = (C.c_int64 * 2)()
+    call("chf_timer_read", C.cast(ms, P), C.cast(n, P))
+    return {"hx_ms": ms[0], "hx_launches": n[0], "gather_ms": ms[1], "gather_launches": n[1]}
+
+
 class Context:
     def __init__(self, device: int = 0):
         self.handle = P()
@@ -279,7 +294,22 @@ class Hamiltonian:
         return it.value
 
     def lda(self, rho, exc, vxc):
-        call("chf_lda", self.handle, _ptr(rho), _ptr(exc), _ptr(vxc), _stream())
+        call("chf_lda", self.handle, _ptr(rho), _ptr(exc) if exc is not None else None, _ptr(vxc), _stream())
+
+    def sad_density(self, pos, species, n_electrons: int, alpha_si: float = 0.074, alpha_h: float = 0.21):
+        import torch
+        a, keep = _atoms(pos, species)
+        rho = torch.zeros(self.n_rows, dtype=torch.float64, device="cuda")
+        call("chf_sad_density", self.handle, C.byref(a), alpha_si, alpha_h, n_electrons, _ptr(rho), _stream())
+        return rho
+
+
+def ion_energy(pos, species, pp) -> float:
+    a, keep = _atoms(pos, species)
+    cp = make_pp(pp)
+    out = C.c_double()
+    call("chf_ion_energy", C.byref(a), C.byref(cp), C.byref(out))
+    return out.value
 
 
 def gram(ctx: Context, A, B, S) -> None:

@@ -34,6 +34,8 @@ def _compile(src: str) -> str:
     cmd = ["hipcc", *HIPFLAGS]
     if src.endswith(".hip"):
         cmd += ["-x", "hip", "-ffp-contract=fast"]
+    else:
+        cmd += ["-fopenmp"]
     cmd += ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -48,7 +50,7 @@ def build(verbose: bool = True) -> str:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp,
-           f"-L{ROCM}/lib", "-lrocblas", "-lrocsolver", f"-Wl,-rpath,{ROCM}/lib"]
+           f"-L{ROCM}/lib", "-lrocblas", "-lrocsolver", "-fopenmp", f"-Wl,-rpath,{ROCM}/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

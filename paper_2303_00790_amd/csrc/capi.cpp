@@ -199,11 +199,23 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
         }
         // projectors
         build_projectors(g, *atoms, *pp, H->proj);
-        const HostProj& P = H->proj;
+        HostProj& P = H->proj;
         upload(H->sup_off, P.sup_off, s);
         upload(H->sup_row, P.sup_row, s);
         upload(H->ent_off, P.ent_off, s);
+        CHF_REQUIRE(P.sup_row.size() < (size_t(1) << 31), "ham_build: more than 2^31 projector pairs");
+        {
+            std::vector<int32_t> off32(P.ent_off.begin(), P.ent_off.end());
+            upload(H->ent_off32, off32, s);
+        }
         upload(H->ent_atom, P.ent_atom, s);
+        if (gd->ordering == CHF_ORDER_HILBERT) {
+            build_block_atoms(g, H->proj);
+            upload(H->ent_slot, H->proj.ent_slot, s);
+            std::vector<int32_t> off32(H->proj.blk_atom_off.begin(), H->proj.blk_atom_off.end());
+            upload(H->blk_atom_off, off32, s);
+            upload(H->blk_atoms, H->proj.blk_atoms, s);
+        }
         const double h3 = gd->h * gd->h * gd->h;
         const double gsc[4] = {h3, h3, h3, h3};
         const double ssc[4] = {pp->h_s, pp->h_p, pp->h_p, pp->h_p};
@@ -375,6 +387,17 @@ int chebyshev_filter(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec
 int chf_filter_generic(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
                        double a0, void* work, int64_t ldw, void* stream) {
     return filter_impl(H, dtype, X, ldx, nvec, degree, a, b, a0, work, ldw, stream, 1);
+}
+
+int chf_timer(int enable) {
+    return guarded([&] { timer_enable(enable); });
+}
+
+int chf_timer_read(double* ms_host, int64_t* launches_host) {
+    return guarded([&] {
+        CHF_REQUIRE(ms_host && launches_host, "chf_timer_read: null argument");
+        timer_read(ms_host, launches_host);
+    });
 }
 
 int chf_ham_apply_generic(chf_ham* H, chf_dtype dtype, const void* X, int64_t ldx, void* Y, int64_t ldy, int nvec,

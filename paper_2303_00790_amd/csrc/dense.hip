@@ -1,2 +1,636 @@
-// placeholder
+// Dense and BLAS-1 pieces of ChFSI on gfx950: deterministic reductions, the
+// Lanczos upper bound, MFMA Gram products, Cholesky-QR and Rayleigh-Ritz.
+//
+// Paper: ChFSI orthonormalises the filtered block and projects H onto it
+// (the CheFSI paragraph; details of the PARSEC implementation are deferred to
+// its ChFSI reference).  The Gram products X^T X and X^T (H X) are the dense
+// contractions of the method and run on MFMA; the M x M Cholesky factorisation
+// and symmetric eigensolve run in FP64 through rocSOLVER; the N x M x M block
+// updates X R^{-1} and X Q are plain GEMMs (rocBLAS).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 #include "internal.hpp"
+#include "kernels.hpp"
+
+namespace chf {
+
+// ---------------------------------------------------------------------------
+// deterministic reductions: fixed grid, per-block tree, then one block sums
+// the partials in order.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+
+__device__ inline double block_sum(double v, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// out[blockIdx.x] = sum over this block's stride of x[i * incx] * y[i * incy]
+template <class T>
+__global__ void __launch_bounds__(256) dot_partial_kernel(int64_t n, const T* __restrict__ x, int64_t incx,
+                                                          const T* __restrict__ y, int64_t incy, double* __restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        acc += double(x[i * incx]) * double(y[i * incy]);
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) sum_partials_kernel(int n, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+template <class T>
+void dot_device(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, int64_t incy, double* out_dev,
+                hipStream_t s) {
+    ctx->red.ensure(kRedBlocks * sizeof(double));
+    const int nb = int(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 255) / 256)));
+    dot_partial_kernel<T><<<nb, 256, 0, s>>>(n, x, incx, y, incy, ctx->red.as<double>());
+    LAUNCH_CHECK();
+    sum_partials_kernel<<<1, 256, 0, s>>>(nb, ctx->red.as<double>(), out_dev);
+    LAUNCH_CHECK();
+}
+
+template <class T>
+double dot_host(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, int64_t incy, hipStream_t s) {
+    ctx->info.ensure(64);
+    double* d = reinterpret_cast<double*>(ctx->info.p);
+    dot_device<T>(ctx, n, x, incx, y, incy, d, s);
+    double h = 0;
+    HIP_CHECK(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return h;
+}
+
+// z[i] = a x[i] + b y[i] (strided)
+__global__ void lincomb_kernel(int64_t n, double a, const double* __restrict__ x, int64_t incx, double b,
+                               const double* __restrict__ y, int64_t incy, double* __restrict__ z, int64_t incz) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double yv = y ? y[i * incy] : 0.0;
+    z[i * incz] = a * x[i * incx] + b * yv;
+}
+
+void lincomb(int64_t n, double a, const double* x, int64_t incx, double b, const double* y, int64_t incy, double* z,
+             int64_t incz, hipStream_t s) {
+    lincomb_kernel<<<unsigned((n + 255) / 256), 256, 0, s>>>(n, a, x, incx, b, y, incy, z, incz);
+    LAUNCH_CHECK();
+}
+
+// Extreme eigenvalues of a symmetric tridiagonal matrix by Sturm-sequence
+// bisection (count of eigenvalues below x = number of negative pivots of
+// T - x I).
+static int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0) ++cnt;
+    for (size_t i = 1; i < d.size(); ++i) {
+        const double qq = (q == 0.0) ? 1e-300 : q;
+        q = d[i] - x - e[i - 1] * e[i - 1] / qq;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+static double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int which /*0 min, 1 max*/) {
+    double lo = d[0], hi = d[0];
+    for (size_t i = 0; i < d.size(); ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < d.size() ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    const int target = which == 0 ? 1 : int(d.size());   // smallest x with count >= target
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (sturm_count(d, e, mid) >= target) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+
+// ---------------------------------------------------------------------------
+// Gram products S = A^T B on MFMA
+//
+// Workgroup: 256 threads = 4 waves (2 x 2), output tile 64 x 64, each wave a
+// 32 x 32 sub-tile = 2 x 2 blocks of the 16 x 16 x 4 MFMA.  The reduction
+// runs over grid rows: every workgroup owns one row slice (split-K); A and B
+// panels of 16 rows are staged in LDS (double-buffered).  FP32 accumulates in
+// FP32 for at most kFlushRows rows and is then added into FP64 registers;
+// partial tiles are written in FP64 and summed over slices in fixed order.
+//
+// MFMA 16x16x4 operand layout (lane l = 0..63): A element (i = l % 16,
+// k = l / 16), B element (k = l / 16, j = l % 16).  Accumulator register v
+// holds D(i, j = l % 16) with i = 4 (l / 16) + v for the FP32 instruction and
+// i = l / 16 + 4 v for the FP64 one (checked on the device).
+// ---------------------------------------------------------------------------
+constexpr int kGT = 64;         // tile edge
+constexpr int kGK = 16;         // rows per LDS panel
+constexpr int kFlushRows = 2048;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <class T>
+struct AccT;
+template <>
+struct AccT<double> {
+    using V = d4;
+};
+template <>
+struct AccT<float> {
+    using V = f4;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) gram_kernel(int64_t n_rows, int m, int n, const T* __restrict__ A, int64_t lda,
+                                                   const T* __restrict__ B, int64_t ldb, int64_t rows_per_slice,
+                                                   const int2* __restrict__ tiles, double* __restrict__ part,
+                                                   int64_t part_stride) {
+    using V = typename AccT<T>::V;
+    __shared__ T As[2][kGK][kGT];
+    __shared__ T Bs[2][kGK][kGT];
+    const int2 tile = tiles[blockIdx.x];
+    const int i0 = tile.x * kGT, j0 = tile.y * kGT;
+    const int slice = blockIdx.y;
+    const int64_t r_begin = int64_t(slice) * rows_per_slice;
+    const int64_t r_end = min(n_rows, r_begin + rows_per_slice);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+
+    V acc[2][2];
+    double acc64[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc[a][b] = V{0, 0, 0, 0};
+            for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
+        }
+
+    // panel loader: 16 x 64 elements of A and of B, 4 each per thread
+    auto load = [&](int64_t r0, int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + 256 * u;        // 0..1023
+            const int rr = e >> 6, cc = e & 63;
+            const int64_t r = r0 + rr;
+            T av = 0, bv = 0;
+            if (r < r_end) {
+                if (i0 + cc < m) av = A[r * lda + i0 + cc];
+                if (j0 + cc < n) bv = B[r * ldb + j0 + cc];
+            }
+            As[buf][rr][cc] = av;
+            Bs[buf][rr][cc] = bv;
+        }
+    };
+
+    int buf = 0;
+    if (r_begin < r_end) load(r_begin, 0);
+    __syncthreads();
+    int64_t since_flush = 0;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGK) {
+        if (r0 + kGK < r_end) load(r0 + kGK, buf ^ 1);
+#pragma unroll
+        for (int kk = 0; kk < kGK / 4; ++kk) {
+            const int krow = kk * 4 + (lane >> 4);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const T av = As[buf][krow][wi * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const T bv = Bs[buf][krow][wj * 32 + b * 16 + (lane & 15)];
+                    acc[a][b] = mfma16(av, bv, acc[a][b]);
+                }
+            }
+        }
+        since_flush += kGK;
+        if (!std::is_same<T, double>::value && since_flush >= kFlushRows) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    for (int v = 0; v < 4; ++v) acc64[a][b][v] += double(acc[a][b][v]);
+                    acc[a][b] = V{0, 0, 0, 0};
+                }
+            since_flush = 0;
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+    double* P = part + int64_t(slice) * part_stride;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ii = std::is_same<T, double>::value ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+                const int i = i0 + wi * 32 + a * 16 + ii;
+                const int j = j0 + wj * 32 + b * 16 + (lane & 15);
+                if (i < m && j < n) P[int64_t(i) * n + j] = acc64[a][b][v] + double(acc[a][b][v]);
+            }
+}
+
+// S[i][j] = sum_slices part[s][i][j] (fixed order); mirror when symmetric.
+__global__ void gram_reduce_kernel(int m, int n, int n_slices, const double* __restrict__ part, int64_t part_stride,
+                                   double* __restrict__ S, int64_t lds, int symmetric) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(m) * n) return;
+    const int i = int(idx / n), j = int(idx % n);
+    if (symmetric && (i / kGT) > (j / kGT)) return;   // tile not computed; mirrored below
+    double s = 0.0;
+    for (int k = 0; k < n_slices; ++k) s += part[int64_t(k) * part_stride + idx];
+    S[int64_t(i) * lds + j] = s;
+    if (symmetric && (i / kGT) < (j / kGT)) S[int64_t(j) * lds + i] = s;
+}
+
+template <class T>
+void gram_product(chf_ctx* ctx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n_rows, int m, int n,
+                  double* S, int64_t lds, hipStream_t s) {
+    const bool symmetric = (A == B) && (m == n) && (lda == ldb);
+    const int tm = (m + kGT - 1) / kGT, tn = (n + kGT - 1) / kGT;
+    std::vector<int2> tiles;
+    for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b)
+            if (!symmetric || a <= b) tiles.push_back(make_int2(a, b));
+    // enough workgroups to fill the chip, slices no shorter than 256 rows
+    int64_t n_slices = std::max<int64_t>(1, (2048 + int64_t(tiles.size()) - 1) / int64_t(tiles.size()));
+    n_slices = std::min<int64_t>(n_slices, std::max<int64_t>(1, n_rows / 256));
+    n_slices = std::min<int64_t>(n_slices, 512);
+    int64_t rows_per_slice = (n_rows + n_slices - 1) / n_slices;
+    rows_per_slice = ((rows_per_slice + kGK - 1) / kGK) * kGK;
+    n_slices = (n_rows + rows_per_slice - 1) / rows_per_slice;
+    if (n_slices < 1) n_slices = 1;
+    const int64_t part_stride = int64_t(m) * n;
+    const size_t tile_bytes = ((tiles.size() * sizeof(int2) + 255) / 256) * 256;
+    ctx->scratch2.ensure(tile_bytes + size_t(n_slices) * size_t(part_stride) * sizeof(double));
+    int2* dtiles = reinterpret_cast<int2*>(ctx->scratch2.p);
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch2.p) + tile_bytes);
+    HIP_CHECK(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    dim3 grid(unsigned(tiles.size()), unsigned(n_slices));
+    gram_kernel<T><<<grid, 256, 0, s>>>(n_rows, m, n, A, lda, B, ldb, rows_per_slice, dtiles, part, part_stride);
+    LAUNCH_CHECK();
+    const int64_t tot = int64_t(m) * n;
+    gram_reduce_kernel<<<unsigned((tot + 255) / 256), 256, 0, s>>>(m, n, int(n_slices), part, part_stride, S, lds,
+                                                                  symmetric ? 1 : 0);
+    LAUNCH_CHECK();
+    // the host tile list must outlive the async copy
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+template void gram_product<float>(chf_ctx*, const float*, int64_t, const float*, int64_t, int64_t, int, int, double*,
+                                  int64_t, hipStream_t);
+template void gram_product<double>(chf_ctx*, const double*, int64_t, const double*, int64_t, int64_t, int, int,
+                                   double*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// small element-wise helpers for the dense steps
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void cast_matrix_kernel(int64_t n, const double* __restrict__ src, T* __restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = T(src[i]);
+}
+
+// column-major upper triangle kept, strictly lower part zeroed (M x M, ld M)
+__global__ void keep_upper_kernel(int m, double* __restrict__ R) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(m) * m) return;
+    const int col = int(idx / m), row = int(idx % m);
+    if (row > col) R[idx] = 0.0;
+}
+
+__global__ void symmetrize_kernel(int m, double* __restrict__ S) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(m) * m) return;
+    const int i = int(idx / m), j = int(idx % m);
+    if (i < j) {
+        const double v = 0.5 * (S[int64_t(i) * m + j] + S[int64_t(j) * m + i]);
+        S[int64_t(i) * m + j] = v;
+        S[int64_t(j) * m + i] = v;
+    }
+}
+
+__global__ void add_diag_kernel(int m, double* __restrict__ S, double shift) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) S[int64_t(i) * m + i] += shift;
+}
+
+__global__ void trace_kernel(int m, const double* __restrict__ S, double* __restrict__ out) {
+    __shared__ double sh[256];
+    double acc = 0;
+    for (int i = threadIdx.x; i < m; i += 256) acc += S[int64_t(i) * m + i];
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = r;
+}
+
+static void check_ctx_block(chf_ctx* ctx, int dtype, const void* X, int64_t ld, int nvec, const char* what) {
+    if (!ctx) fail(CHF_EINVAL, "%s: null context", what);
+    if (dtype != CHF_F32 && dtype != CHF_F64) fail(CHF_EINVAL, "%s: bad dtype", what);
+    if (!X) fail(CHF_EINVAL, "%s: null block", what);
+    if (nvec < 1 || ld < nvec) fail(CHF_EINVAL, "%s: need 1 <= nvec <= ld", what);
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev != ctx->device) fail(CHF_EINVAL, "%s: context belongs to device %d, current is %d", what, ctx->device, dev);
+}
+
+template <class F>
+static int guard(F&& f) {
+    try {
+        f();
+        return CHF_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return CHF_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return CHF_EHIP;
+    }
+}
+
+// S (row-major M x M, FP64) lives at the start of ctx->scratch; the rest holds
+// the cast factor for FP32 updates and rocSOLVER's info word.
+static double* mm_scratch(chf_ctx* ctx, int m, size_t extra_bytes) {
+    const size_t mm = size_t(m) * m * sizeof(double);
+    ctx->scratch.ensure(mm + size_t(m) * m * sizeof(float) + extra_bytes + 256);
+    return ctx->scratch.as<double>();
+}
+
+// Cholesky-QR on one block: S = X^T X, S = R^T R, X <- X R^{-1}.  Returns 0 or
+// the rocSOLVER info (> 0: leading minor not positive definite).
+template <class T>
+static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, double shift_rel, hipStream_t s) {
+    double* S = mm_scratch(ctx, m, 0);
+    gram_product<T>(ctx, X, ldx, X, ldx, n_rows, m, m, S, m, s);
+    if (shift_rel > 0) {
+        ctx->info.ensure(64);
+        double* tr = reinterpret_cast<double*>(ctx->info.p);
+        trace_kernel<<<1, 256, 0, s>>>(m, S, tr);
+        double htr = 0;
+        HIP_CHECK(hipMemcpyAsync(&htr, tr, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        add_diag_kernel<<<(m + 255) / 256, 256, 0, s>>>(m, S, shift_rel * htr / m);
+        LAUNCH_CHECK();
+    }
+    ROCBLAS_CHECK(rocblas_set_stream(ctx->blas, s));
+    // row-major S equals its column-major view (symmetric); potrf(upper) gives
+    // column-major U with S = U^T U, i.e. R = U.
+    int* dinfo = reinterpret_cast<int*>(reinterpret_cast<char*>(S) + size_t(m) * m * sizeof(double) +
+                                        size_t(m) * m * sizeof(float));
+    ROCBLAS_CHECK(rocsolver_dpotrf(ctx->blas, rocblas_fill_upper, m, S, m, dinfo));
+    int info = 0;
+    HIP_CHECK(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (info != 0) return info;
+    keep_upper_kernel<<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(m, S);
+    LAUNCH_CHECK();
+    // X is row-major [n_rows][ldx] = column-major Xc [m][n_rows] (ld ldx).
+    // X R^{-1}  <=>  Xc <- R^{-T} Xc : left-side solve with U^T.
+    if (std::is_same<T, double>::value) {
+        const double one = 1.0;
+        ROCBLAS_CHECK(rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                                    rocblas_diagonal_non_unit, m, rocblas_int(n_rows), &one, S, m,
+                                    reinterpret_cast<double*>(X), rocblas_int(ldx)));
+    } else {
+        float* R32 = reinterpret_cast<float*>(reinterpret_cast<char*>(S) + size_t(m) * m * sizeof(double));
+        cast_matrix_kernel<float><<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(int64_t(m) * m, S, R32);
+        LAUNCH_CHECK();
+        const float one = 1.0f;
+        ROCBLAS_CHECK(rocblas_strsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                                    rocblas_diagonal_non_unit, m, rocblas_int(n_rows), &one, R32, m,
+                                    reinterpret_cast<float*>(X), rocblas_int(ldx)));
+    }
+    return 0;
+}
+
+template <class T>
+void orthonormalize_t(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, int* fallbacks, hipStream_t s) {
+    int fb = 0;
+    int info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, s);
+    if (info != 0) {
+        // shifted Cholesky-QR followed by a plain pass (CholQR2 on the
+        // shifted factor): the shift makes the factorisation exist, the
+        // second pass restores orthonormality.
+        ++fb;
+        const double shift = std::is_same<T, double>::value ? 1e-14 : 1e-6;
+        info = cholqr_once<T>(ctx, X, ldx, n_rows, m, shift, s);
+        if (info == 0) info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, s);
+    }
+    if (fallbacks) *fallbacks = fb;
+    if (info != 0) fail(CHF_ENOTPD, "orthonormalize: Gram matrix not positive definite (minor %d)", info);
+}
+
+template <class T>
+void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double* eig_host, T* W, int64_t ldw,
+                            hipStream_t s) {
+    const int64_t n_rows = H->grid.n_rows;
+    double* Hs = mm_scratch(ctx, m, size_t(m) * sizeof(double) * 2);
+    double* evals = reinterpret_cast<double*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * (sizeof(double) + sizeof(float)) + 256);
+    double* E = evals + m;
+    int* dinfo = reinterpret_cast<int*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * (sizeof(double) + sizeof(float)));
+    // Hs[:, c:c+nb] = X^T (H X[:, c:c+nb]), blockwise through W
+    const int nb = int(std::min<int64_t>(m, ldw));
+    for (int c = 0; c < m; c += nb) {
+        const int w = std::min(nb, m - c);
+        hx_step<T>(H, X + c, ldx, W, ldw, nullptr, 0, w, 1.0, 0.0, 0.0, s, 0);
+        gram_product<T>(ctx, X, ldx, W, ldw, n_rows, m, w, Hs + c, m, s);
+    }
+    symmetrize_kernel<<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(m, Hs);
+    LAUNCH_CHECK();
+    ROCBLAS_CHECK(rocblas_set_stream(ctx->blas, s));
+    ROCBLAS_CHECK(rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, m, Hs, m, evals, E, dinfo));
+    int info = 0;
+    HIP_CHECK(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(eig_host, evals, size_t(m) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (info != 0) fail(CHF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge (info %d)", info);
+    for (int i = 0; i < m; ++i)
+        if (!std::isfinite(eig_host[i])) fail(CHF_ENONFINITE, "rayleigh_ritz: non-finite Ritz value");
+    // Hs now holds Q column-major (column j = eigenvector j).  X Q (row-major)
+    // <=> Xc_new = Q^T Xc, computed into W in row panels of ldw / m ... W must
+    // hold all m columns: ldw >= m is required for the rotation.
+    if (ldw < m) fail(CHF_EINVAL, "rayleigh_ritz: work leading dimension must be >= nvec");
+    if (std::is_same<T, double>::value) {
+        const double one = 1.0, zero = 0.0;
+        ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, m,
+                                    rocblas_int(n_rows), m, &one, Hs, m, reinterpret_cast<const double*>(X),
+                                    rocblas_int(ldx), &zero, reinterpret_cast<double*>(W), rocblas_int(ldw)));
+    } else {
+        float* Q32 = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * sizeof(double));
+        cast_matrix_kernel<float><<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(int64_t(m) * m, Hs, Q32);
+        LAUNCH_CHECK();
+        const float one = 1.0f, zero = 0.0f;
+        ROCBLAS_CHECK(rocblas_sgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, m,
+                                    rocblas_int(n_rows), m, &one, Q32, m, reinterpret_cast<const float*>(X),
+                                    rocblas_int(ldx), &zero, reinterpret_cast<float*>(W), rocblas_int(ldw)));
+    }
+    HIP_CHECK(hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), W, size_t(ldw) * sizeof(T), size_t(m) * sizeof(T),
+                               size_t(n_rows), hipMemcpyDeviceToDevice, s));
+}
+
+void lanczos_run(chf_ham* H, chf_ctx* ctx, const double* v0, int k, double* out3, hipStream_t s) {
+    const int64_t n = H->grid.n_rows;
+    // three vectors stored as 2-column blocks (second column zero) so the
+    // tiled kernel's 16-byte rows apply
+    ctx->vec.ensure(size_t(n) * 2 * 3 * sizeof(double));
+    double* base = ctx->vec.as<double>();
+    HIP_CHECK(hipMemsetAsync(base, 0, size_t(n) * 2 * 3 * sizeof(double), s));
+    double* v = base;
+    double* vp = base + 2 * n;
+    double* f = base + 4 * n;
+    const double nrm = std::sqrt(dot_host<double>(ctx, n, v0, 1, v0, 1, s));
+    if (!(nrm > 0) || !std::isfinite(nrm)) fail(CHF_EINVAL, "lanczos_bound: zero or non-finite start vector");
+    lincomb(n, 1.0 / nrm, v0, 1, 0.0, nullptr, 0, v, 2, s);
+    std::vector<double> d, e;
+    hx_step<double>(H, v, 2, f, 2, nullptr, 0, 2, 1.0, 0.0, 0.0, s, 0);
+    double alpha = dot_host<double>(ctx, n, v, 2, f, 2, s);
+    lincomb(n, 1.0, f, 2, -alpha, v, 2, f, 2, s);
+    d.push_back(alpha);
+    for (int j = 1; j < k; ++j) {
+        const double beta = std::sqrt(dot_host<double>(ctx, n, f, 2, f, 2, s));
+        if (!(beta > 0)) break;   // invariant subspace found
+        std::swap(v, vp);
+        lincomb(n, 1.0 / beta, f, 2, 0.0, nullptr, 0, v, 2, s);
+        hx_step<double>(H, v, 2, f, 2, nullptr, 0, 2, 1.0, 0.0, 0.0, s, 0);
+        lincomb(n, 1.0, f, 2, -beta, vp, 2, f, 2, s);
+        alpha = dot_host<double>(ctx, n, v, 2, f, 2, s);
+        lincomb(n, 1.0, f, 2, -alpha, v, 2, f, 2, s);
+        d.push_back(alpha);
+        e.push_back(beta);
+    }
+    const double fn = std::sqrt(dot_host<double>(ctx, n, f, 2, f, 2, s));
+    const double tmax = tridiag_eig(d, e, 1), tmin = tridiag_eig(d, e, 0);
+    out3[0] = tmax + fn;
+    out3[1] = tmin;
+    out3[2] = tmax;
+    if (!std::isfinite(out3[0])) fail(CHF_ENONFINITE, "lanczos_bound: non-finite result");
+}
+
+}  // namespace chf
+
+using namespace chf;
+
+extern "C" {
+
+int chf_ctx_create(int device, chf_ctx** out) {
+    try {
+        if (!out) fail(CHF_EINVAL, "chf_ctx_create: null out");
+        *out = nullptr;
+        int n = 0;
+        HIP_CHECK(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) fail(CHF_EINVAL, "chf_ctx_create: device %d out of range (%d devices)", device, n);
+        HIP_CHECK(hipSetDevice(device));
+        auto* c = new chf_ctx;
+        c->device = device;
+        if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+            delete c;
+            fail(CHF_EHIP, "rocblas_create_handle failed");
+        }
+        *out = c;
+        return CHF_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (...) {
+        set_last_error("chf_ctx_create: unknown error");
+        return CHF_EHIP;
+    }
+}
+
+int chf_ctx_destroy(chf_ctx* ctx) {
+    if (!ctx) return CHF_OK;
+    (void)hipDeviceSynchronize();
+    if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+    delete ctx;
+    return CHF_OK;
+}
+
+
+int gram(chf_ctx* ctx, chf_dtype dtype, const void* A, int64_t lda, const void* B, int64_t ldb, int64_t n_rows, int m,
+         int n, double* S, int64_t lds, void* stream) {
+    return guard([&] {
+        check_ctx_block(ctx, dtype, A, lda, m, "gram A");
+        check_ctx_block(ctx, dtype, B, ldb, n, "gram B");
+        if (!S || lds < n || n_rows < 1) fail(CHF_EINVAL, "gram: bad output or row count");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (dtype == CHF_F64)
+            gram_product<double>(ctx, static_cast<const double*>(A), lda, static_cast<const double*>(B), ldb, n_rows, m, n,
+                                 S, lds, s);
+        else
+            gram_product<float>(ctx, static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb, n_rows, m, n,
+                                S, lds, s);
+    });
+}
+
+int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X, int64_t ldx, int64_t n_rows, int nvec, int* fallbacks,
+                   void* stream) {
+    return guard([&] {
+        check_ctx_block(ctx, dtype, X, ldx, nvec, "orthonormalize");
+        if (n_rows < nvec) fail(CHF_EINVAL, "orthonormalize: n_rows < nvec");
+        if (n_rows >= (int64_t(1) << 31) || ldx >= (int64_t(1) << 31)) fail(CHF_EINVAL, "orthonormalize: block too large");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (dtype == CHF_F64)
+            orthonormalize_t<double>(ctx, static_cast<double*>(X), ldx, n_rows, nvec, fallbacks, s);
+        else
+            orthonormalize_t<float>(ctx, static_cast<float*>(X), ldx, n_rows, nvec, fallbacks, s);
+    });
+}
+
+int rayleigh_ritz(chf_ham* H, chf_ctx* ctx, chf_dtype dtype, void* X, int64_t ldx, int nvec, double* eig_host,
+                  void* work, int64_t ldw, void* stream) {
+    return guard([&] {
+        if (!H || !eig_host) fail(CHF_EINVAL, "rayleigh_ritz: null argument");
+        check_ctx_block(ctx, dtype, X, ldx, nvec, "rayleigh_ritz X");
+        check_ctx_block(ctx, dtype, work, ldw, std::min(nvec, int(ldw)), "rayleigh_ritz work");
+        if (!(H->dtypes & (dtype == CHF_F64 ? 2 : 1))) fail(CHF_EINVAL, "rayleigh_ritz: handle not built for dtype");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (dtype == CHF_F64)
+            rayleigh_ritz_t<double>(H, ctx, static_cast<double*>(X), ldx, nvec, eig_host, static_cast<double*>(work), ldw, s);
+        else
+            rayleigh_ritz_t<float>(H, ctx, static_cast<float*>(X), ldx, nvec, eig_host, static_cast<float*>(work), ldw, s);
+    });
+}
+
+int lanczos_bound(chf_ham* H, chf_ctx* ctx, const double* v0, int k, double* out3, void* stream) {
+    return guard([&] {
+        if (!H || !ctx || !v0 || !out3) fail(CHF_EINVAL, "lanczos_bound: null argument");
+        if (k < 2 || k > 64) fail(CHF_EINVAL, "lanczos_bound: k must be in [2, 64]");
+        if (!(H->dtypes & 2)) fail(CHF_EINVAL, "lanczos_bound: the handle was not built for FP64");
+        lanczos_run(H, ctx, v0, k, out3, static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // extern "C"
+
+namespace chf {
+template void dot_device<double>(chf_ctx*, int64_t, const double*, int64_t, const double*, int64_t, double*, hipStream_t);
+template void dot_device<float>(chf_ctx*, int64_t, const float*, int64_t, const float*, int64_t, double*, hipStream_t);
+template double dot_host<double>(chf_ctx*, int64_t, const double*, int64_t, const double*, int64_t, hipStream_t);
+template void orthonormalize_t<float>(chf_ctx*, float*, int64_t, int64_t, int, int*, hipStream_t);
+template void orthonormalize_t<double>(chf_ctx*, double*, int64_t, int64_t, int, int*, hipStream_t);
+template void rayleigh_ritz_t<float>(chf_ham*, chf_ctx*, float*, int64_t, int, double*, float*, int64_t, hipStream_t);
+template void rayleigh_ritz_t<double>(chf_ham*, chf_ctx*, double*, int64_t, int, double*, double*, int64_t, hipStream_t);
+}  // namespace chf

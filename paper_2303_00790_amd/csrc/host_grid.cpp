@@ -11,6 +11,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <numeric>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "internal.hpp"
 
@@ -197,20 +200,23 @@ void build_projectors(const HostGrid& g, const chf_atoms& atoms, const chf_pp& p
     const double y00 = 1.0 / std::sqrt(4.0 * pi);
     const double y1 = std::sqrt(3.0 / (4.0 * pi));
     out = HostProj{};
-    std::vector<int64_t> row_count(size_t(g.n_rows) + 1, 0);
-    out.sup_off.push_back(0);
-    std::vector<std::pair<int32_t, int>> tmp;  // (row, local index)
-    std::vector<double> tmpb;
-    for (int a = 0; a < atoms.n_atoms; ++a) {
-        if (atoms.species_host[a] != 0) continue;
-        const double* X = atoms.pos_host + 3 * a;
+    for (int a = 0; a < atoms.n_atoms; ++a)
+        if (atoms.species_host[a] == 0) out.atom_index.push_back(a);
+    out.n_proj = int64_t(out.atom_index.size());
+    const int64_t np_atoms = out.n_proj;
+    // per projector atom: support rows ascending and the four projector values
+    std::vector<std::vector<int32_t>> rows_of(static_cast<size_t>(np_atoms));
+    std::vector<std::vector<double>> beta_of(static_cast<size_t>(np_atoms));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t pa = 0; pa < np_atoms; ++pa) {
+        const double* X = atoms.pos_host + 3 * out.atom_index[size_t(pa)];
         int lo[3], hi[3];
         for (int d = 0; d < 3; ++d) {
             lo[d] = std::max(-g.n_r, int(std::floor((X[d] - pp.r_cut) / h)) - 1);
             hi[d] = std::min(g.n_r, int(std::ceil((X[d] + pp.r_cut) / h)) + 1);
         }
-        tmp.clear();
-        tmpb.clear();
+        std::vector<std::pair<int32_t, int>> tmp;
+        std::vector<double> tmpb;
         for (int k = lo[2]; k <= hi[2]; ++k)
             for (int j = lo[1]; j <= hi[1]; ++j)
                 for (int i = lo[0]; i <= hi[0]; ++i) {
@@ -228,28 +234,76 @@ void build_projectors(const HostGrid& g, const chf_atoms& atoms, const chf_pp& p
                     tmpb.push_back(np * y1 * gauss * dz);
                 }
         std::sort(tmp.begin(), tmp.end());
+        auto& R = rows_of[size_t(pa)];
+        auto& Bv = beta_of[size_t(pa)];
+        R.reserve(tmp.size());
+        Bv.reserve(4 * tmp.size());
         for (auto& rl : tmp) {
-            out.sup_row.push_back(rl.first);
-            for (int m = 0; m < 4; ++m) out.sup_beta.push_back(tmpb[size_t(4 * rl.second + m)]);
-            row_count[size_t(rl.first) + 1]++;
+            R.push_back(rl.first);
+            for (int m = 0; m < 4; ++m) Bv.push_back(tmpb[size_t(4 * rl.second + m)]);
         }
-        out.atom_index.push_back(a);
-        out.sup_off.push_back(int64_t(out.sup_row.size()));
     }
-    out.n_proj = int64_t(out.atom_index.size());
-    const int64_t pairs = int64_t(out.sup_row.size());
+    out.sup_off.assign(size_t(np_atoms) + 1, 0);
+    for (int64_t pa = 0; pa < np_atoms; ++pa)
+        out.sup_off[size_t(pa) + 1] = out.sup_off[size_t(pa)] + int64_t(rows_of[size_t(pa)].size());
+    const int64_t pairs = out.sup_off.back();
+    out.sup_row.resize(size_t(pairs));
+    out.sup_beta.resize(size_t(pairs) * 4);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t pa = 0; pa < np_atoms; ++pa) {
+        std::copy(rows_of[size_t(pa)].begin(), rows_of[size_t(pa)].end(), out.sup_row.begin() + out.sup_off[size_t(pa)]);
+        std::copy(beta_of[size_t(pa)].begin(), beta_of[size_t(pa)].end(),
+                  out.sup_beta.begin() + 4 * out.sup_off[size_t(pa)]);
+        std::vector<int32_t>().swap(rows_of[size_t(pa)]);
+        std::vector<double>().swap(beta_of[size_t(pa)]);
+    }
     // scatter entries bucketed by row, atoms ascending within a row
-    for (int64_t r = 0; r < g.n_rows; ++r) row_count[size_t(r) + 1] += row_count[size_t(r)];
-    out.ent_off = row_count;
+    out.ent_off.assign(size_t(g.n_rows) + 1, 0);
+    for (int64_t e = 0; e < pairs; ++e) out.ent_off[size_t(out.sup_row[size_t(e)]) + 1]++;
+    for (int64_t r = 0; r < g.n_rows; ++r) out.ent_off[size_t(r) + 1] += out.ent_off[size_t(r)];
     out.ent_atom.assign(size_t(pairs), 0);
     out.ent_beta.assign(size_t(pairs) * 4, 0.0);
-    std::vector<int64_t> fill(out.ent_off.begin(), out.ent_off.end() - 1);
-    for (int64_t pa = 0; pa < out.n_proj; ++pa)
-        for (int64_t e = out.sup_off[size_t(pa)]; e < out.sup_off[size_t(pa) + 1]; ++e) {
-            const int64_t dst = fill[size_t(out.sup_row[size_t(e)])]++;
-            out.ent_atom[size_t(dst)] = int32_t(pa);
-            for (int m = 0; m < 4; ++m) out.ent_beta[size_t(4 * dst + m)] = out.sup_beta[size_t(4 * e + m)];
+    // each thread owns a contiguous range of rows and scans all pairs in
+    // atom order, so the entries of a row stay atom-ascending
+#pragma omp parallel
+    {
+        int nt = 1, tid = 0;
+#ifdef _OPENMP
+        nt = omp_get_num_threads();
+        tid = omp_get_thread_num();
+#endif
+        const int64_t r0 = g.n_rows * tid / nt, r1 = g.n_rows * (tid + 1) / nt;
+        std::vector<int64_t> fill(out.ent_off.begin() + r0, out.ent_off.begin() + r1);
+        for (int64_t pa = 0; pa < np_atoms; ++pa)
+            for (int64_t e = out.sup_off[size_t(pa)]; e < out.sup_off[size_t(pa) + 1]; ++e) {
+                const int64_t r = out.sup_row[size_t(e)];
+                if (r < r0 || r >= r1) continue;
+                const int64_t dst = fill[size_t(r - r0)]++;
+                out.ent_atom[size_t(dst)] = int32_t(pa);
+                for (int m = 0; m < 4; ++m) out.ent_beta[size_t(4 * dst + m)] = out.sup_beta[size_t(4 * e + m)];
+            }
+    }
+}
+
+void build_block_atoms(const HostGrid& g, HostProj& P) {
+    P.blk_atom_off.assign(size_t(g.n_blocks) + 1, 0);
+    P.blk_atoms.clear();
+    P.ent_slot.assign(P.ent_atom.size(), 0);
+    P.max_block_atoms = 0;
+    std::vector<int32_t> list;
+    for (int64_t b = 0; b < g.n_blocks; ++b) {
+        const int64_t e0 = P.ent_off[size_t(b * kBlockPts)], e1 = P.ent_off[size_t((b + 1) * kBlockPts)];
+        list.assign(P.ent_atom.begin() + e0, P.ent_atom.begin() + e1);
+        std::sort(list.begin(), list.end());
+        list.erase(std::unique(list.begin(), list.end()), list.end());
+        P.max_block_atoms = std::max(P.max_block_atoms, int(list.size()));
+        for (int64_t e = e0; e < e1; ++e) {
+            const auto it = std::lower_bound(list.begin(), list.end(), P.ent_atom[size_t(e)]);
+            P.ent_slot[size_t(e)] = uint8_t(std::min<ptrdiff_t>(255, it - list.begin()));
         }
+        P.blk_atoms.insert(P.blk_atoms.end(), list.begin(), list.end());
+        P.blk_atom_off[size_t(b) + 1] = int64_t(P.blk_atoms.size());
+    }
 }
 
 }  // namespace chf

@@ -96,56 +96,6 @@ void launch_cast_veff(chf_ham* H, const double* src, double* d64, float* d32, in
 }
 
 // ---------------------------------------------------------------------------
-// KB gather: C[a][lm][v] = sum_j (h^3 beta_alm(row_j)) X[row_j][v]
-// 256 threads = 64 vector lanes x 4 slices of the support list; the slices
-// are summed in fixed order (deterministic).
-// ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256) kb_gather_kernel(const int64_t* __restrict__ sup_off,
-                                                        const int32_t* __restrict__ sup_row,
-                                                        const T* __restrict__ sup_beta, const T* __restrict__ X,
-                                                        int64_t ldx, int nvec, T* __restrict__ C) {
-    __shared__ T part[4][4][64];
-    const int a = blockIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int slice = threadIdx.x >> 6;
-    const int v = blockIdx.y * 64 + lane;
-    const int64_t j0 = sup_off[a], j1 = sup_off[a + 1];
-    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    if (v < nvec) {
-        for (int64_t j = j0 + slice; j < j1; j += 4) {
-            const T x = X[int64_t(sup_row[j]) * ldx + v];
-            const T* b = sup_beta + 4 * j;
-            s0 += b[0] * x;
-            s1 += b[1] * x;
-            s2 += b[2] * x;
-            s3 += b[3] * x;
-        }
-    }
-    part[slice][0][lane] = s0;
-    part[slice][1][lane] = s1;
-    part[slice][2][lane] = s2;
-    part[slice][3][lane] = s3;
-    __syncthreads();
-    if (slice == 0 && v < nvec) {
-        for (int lm = 0; lm < 4; ++lm) {
-            const T t = ((part[0][lm][lane] + part[1][lm][lane]) + part[2][lm][lane]) + part[3][lm][lane];
-            C[(int64_t(a) * 4 + lm) * nvec + v] = t;
-        }
-    }
-}
-
-template <class T>
-void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipStream_t s) {
-    if (H->proj.n_proj == 0) return;
-    const T* beta = std::is_same<T, double>::value ? H->sup_beta64.as<T>() : H->sup_beta32.as<T>();
-    dim3 grid(unsigned(H->proj.n_proj), unsigned((nvec + 63) / 64));
-    kb_gather_kernel<T><<<grid, dim3(256), 0, s>>>(H->sup_off.as<int64_t>(), H->sup_row.as<int32_t>(), beta, X, ldx,
-                                                   nvec, C);
-    LAUNCH_CHECK();
-}
-
-// ---------------------------------------------------------------------------
 // generic neighbour-table H X with fused recurrence epilogue
 // ---------------------------------------------------------------------------
 template <class T>
@@ -192,8 +142,11 @@ __global__ void __launch_bounds__(256) hx_generic_kernel(int64_t n_rows, int nve
                 if (v0 + e < nvec) acc[e] += k.c[kk] * q[v0 + e];
         }
     }
-    const T vr = veff[row];
-    for (int e = 0; e < VPT; ++e) acc[e] += vr * xc[e];
+    if (veff) {
+        const T vr = veff[row];
+        for (int e = 0; e < VPT; ++e) acc[e] += vr * xc[e];
+    }
+    if (ent_off)
     for (int64_t en = ent_off[row]; en < ent_off[row + 1]; ++en) {
         const int64_t a = ent_atom[en];
         const T* b = ent_beta + 4 * en;
@@ -233,12 +186,13 @@ static const T* ent_beta_of(const chf_ham* H) {
 
 template <class T>
 void launch_hx_generic(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
-                       const T* C, double alpha, double shift, double beta, hipStream_t s) {
+                       const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only) {
     const int nvc = (nvec + 3) / 4;
     const int64_t total = H->grid.n_rows * nvc;
     hx_generic_kernel<T><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, s>>>(
-        H->grid.n_rows, nvec, nvc, H->nbr_rows.as<int32_t>(), H->row_inside.as<uint8_t>(), veff_of<T>(H),
-        H->ent_off.as<int64_t>(), H->ent_atom.as<int32_t>(), ent_beta_of<T>(H), C, X, ldx, Y, ldy, Z, ldz,
+        H->grid.n_rows, nvec, nvc, H->nbr_rows.as<int32_t>(), H->row_inside.as<uint8_t>(),
+        lap_only ? nullptr : veff_of<T>(H), lap_only ? nullptr : H->ent_off.as<int64_t>(), H->ent_atom.as<int32_t>(),
+        ent_beta_of<T>(H), C, X, ldx, Y, ldy, Z, ldz,
         make_coef<T>(H, alpha, shift, beta));
     LAUNCH_CHECK();
 }
@@ -290,6 +244,119 @@ __device__ inline double2 vadd(double2 a, double2 b) { return make_double2(a.x +
 __device__ inline float4 vscale(float s, float4 a) { return make_float4(s * a.x, s * a.y, s * a.z, s * a.w); }
 __device__ inline double2 vscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
+// ---------------------------------------------------------------------------
+// KB gather: C[a][lm][v] = sum_j (h^3 beta_alm(row_j)) X[row_j][v]
+// One workgroup per (projector atom, 64-quad vector chunk): 4 waves split the
+// support list (row j goes to wave j % 4), each lane owns one 16-byte quad of
+// vectors, and every lane keeps four independent row loads in flight.  The
+// four wave partials are summed in fixed order (deterministic).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) kb_gather_kernel(const int64_t* __restrict__ sup_off,
+                                                        const int32_t* __restrict__ sup_row,
+                                                        const T* __restrict__ sup_beta, const T* __restrict__ X,
+                                                        int64_t ldx, int nvec, T* __restrict__ C) {
+    using V = typename Quad<T>::V;
+    constexpr int QN = Quad<T>::N;
+    __shared__ V part[4][4][64];
+    const int a = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int v = (blockIdx.y * 64 + lane) * QN;
+    const bool ok = v < nvec;
+    const int64_t j0 = sup_off[a], j1 = sup_off[a + 1];
+    V s0 = vzero<V>(), s1 = vzero<V>(), s2 = vzero<V>(), s3 = vzero<V>();
+    int64_t j = j0 + wave;
+    for (; j + 12 < j1; j += 16) {
+        V x[4];
+        T bt[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t jj = j + 4 * u;
+            x[u] = ok ? *reinterpret_cast<const V*>(X + int64_t(sup_row[jj]) * ldx + v) : vzero<V>();
+#pragma unroll
+            for (int m = 0; m < 4; ++m) bt[u][m] = sup_beta[4 * jj + m];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s0 = vfma(bt[u][0], x[u], s0);
+            s1 = vfma(bt[u][1], x[u], s1);
+            s2 = vfma(bt[u][2], x[u], s2);
+            s3 = vfma(bt[u][3], x[u], s3);
+        }
+    }
+    for (; j < j1; j += 4) {
+        const V x = ok ? *reinterpret_cast<const V*>(X + int64_t(sup_row[j]) * ldx + v) : vzero<V>();
+        const T* b = sup_beta + 4 * j;
+        s0 = vfma(b[0], x, s0);
+        s1 = vfma(b[1], x, s1);
+        s2 = vfma(b[2], x, s2);
+        s3 = vfma(b[3], x, s3);
+    }
+    part[wave][0][lane] = s0;
+    part[wave][1][lane] = s1;
+    part[wave][2][lane] = s2;
+    part[wave][3][lane] = s3;
+    __syncthreads();
+    if (ok) {
+        const int lm = wave;   // each wave finishes one channel
+        const V t = vadd(vadd(vadd(part[0][lm][lane], part[1][lm][lane]), part[2][lm][lane]), part[3][lm][lane]);
+        *reinterpret_cast<V*>(C + (int64_t(a) * 4 + lm) * nvec + v) = t;
+    }
+}
+
+// scalar variant for blocks whose width or alignment rules out 16-byte quads
+template <class T>
+__global__ void __launch_bounds__(256) kb_gather_scalar_kernel(const int64_t* __restrict__ sup_off,
+                                                               const int32_t* __restrict__ sup_row,
+                                                               const T* __restrict__ sup_beta,
+                                                               const T* __restrict__ X, int64_t ldx, int nvec,
+                                                               T* __restrict__ C) {
+    __shared__ T part[4][4][64];
+    const int a = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int slice = threadIdx.x >> 6;
+    const int v = blockIdx.y * 64 + lane;
+    const int64_t j0 = sup_off[a], j1 = sup_off[a + 1];
+    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    if (v < nvec) {
+        for (int64_t j = j0 + slice; j < j1; j += 4) {
+            const T x = X[int64_t(sup_row[j]) * ldx + v];
+            const T* b = sup_beta + 4 * j;
+            s0 += b[0] * x;
+            s1 += b[1] * x;
+            s2 += b[2] * x;
+            s3 += b[3] * x;
+        }
+    }
+    part[slice][0][lane] = s0;
+    part[slice][1][lane] = s1;
+    part[slice][2][lane] = s2;
+    part[slice][3][lane] = s3;
+    __syncthreads();
+    if (v < nvec) {
+        const int lm = slice;
+        C[(int64_t(a) * 4 + lm) * nvec + v] = ((part[0][lm][lane] + part[1][lm][lane]) + part[2][lm][lane]) + part[3][lm][lane];
+    }
+}
+
+template <class T>
+void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipStream_t s) {
+    if (H->proj.n_proj == 0) return;
+    constexpr int QN = Quad<T>::N;
+    const T* beta = std::is_same<T, double>::value ? H->sup_beta64.as<T>() : H->sup_beta32.as<T>();
+    if (nvec % QN == 0 && ldx % QN == 0 && uintptr_t(X) % 16 == 0) {
+        dim3 grid(unsigned(H->proj.n_proj), unsigned((nvec / QN + 63) / 64));
+        kb_gather_kernel<T><<<grid, dim3(256), 0, s>>>(H->sup_off.as<int64_t>(), H->sup_row.as<int32_t>(), beta, X, ldx,
+                                                       nvec, C);
+    } else {
+        dim3 grid(unsigned(H->proj.n_proj), unsigned((nvec + 63) / 64));
+        kb_gather_scalar_kernel<T><<<grid, dim3(256), 0, s>>>(H->sup_off.as<int64_t>(), H->sup_row.as<int32_t>(), beta,
+                                                              X, ldx, nvec, C);
+    }
+    LAUNCH_CHECK();
+}
+
 __device__ inline int lds_row(int x, int y) {
     // x in [-6, 14), y in [-6, 14), not both outside [0, 8)
     if (y >= 0 && y < 8) return (x + 6) + 20 * y;
@@ -297,166 +364,369 @@ __device__ inline int lds_row(int x, int y) {
     return 208 + x + 8 * (y - 8);
 }
 
+// 8-byte lane values of the tiled kernel: two floats or one double
 template <class T>
-__global__ void __launch_bounds__(512) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
-                                                       const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
-                                                       const int64_t* __restrict__ ent_off,
-                                                       const int32_t* __restrict__ ent_atom,
-                                                       const T* __restrict__ ent_beta, const T* __restrict__ C,
-                                                       int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
-                                                       int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
-    using V = typename Quad<T>::V;
-    constexpr int QN = Quad<T>::N;       // elements per quad
-    constexpr int CH = 8 * QN;           // vectors per chunk
-    __shared__ V plane[2][256][8];
+struct Lane;
+template <>
+struct Lane<float> {
+    using V = float2;
+    static constexpr int N = 2;
+};
+template <>
+struct Lane<double> {
+    using V = double;
+    static constexpr int N = 1;
+};
+__device__ inline void lzero(float2& v) { v = make_float2(0.f, 0.f); }
+__device__ inline void lzero(double& v) { v = 0.0; }
+__device__ inline float2 lfma(float s, float2 a, float2 c) { return make_float2(fmaf(s, a.x, c.x), fmaf(s, a.y, c.y)); }
+__device__ inline double lfma(double s, double a, double c) { return fma(s, a, c); }
+__device__ inline float2 ladd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline double ladd(double a, double b) { return a + b; }
+__device__ inline float2 lscale(float s, float2 a) { return make_float2(s * a.x, s * a.y); }
+__device__ inline double lscale(double s, double a) { return s * a; }
+
+template <class V>
+__device__ inline V lz() {
+    V v;
+    lzero(v);
+    return v;
+}
+
+// raw buffer access (vector memory through a 128-bit resource descriptor)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(bytes), 0x00020000);
+}
+template <class V>
+__device__ inline V bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <class V>
+__device__ inline void bstore(V v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// Workgroup of 1024 threads = 64 columns x 16 lanes; a lane holds 8 bytes
+// (2 floats or 1 double) of a 128-byte vector chunk (32 FP32 / 16 FP64
+// vectors); one workgroup per tile (one 8^3 block x one vector chunk), 16
+// waves.  The KB coefficients of the atoms touching the block can be staged
+// in LDS (STAGE, up to kMaxBlockAtoms) instead of read from global memory.
+constexpr int kMaxBlockAtoms = 64;
+
+template <class T, bool STAGE>
+__global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
+                                                        const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
+                                                        const int32_t* __restrict__ ent_off,
+                                                        const int32_t* __restrict__ ent_atom,
+                                                        const uint8_t* __restrict__ ent_slot,
+                                                        const T* __restrict__ ent_beta,
+                                                        const int32_t* __restrict__ blk_atom_off,
+                                                        const int32_t* __restrict__ blk_atoms, const T* __restrict__ C,
+                                                        int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
+                                                        int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
+    using V = typename Lane<T>::V;
+    constexpr int LN = Lane<T>::N;       // elements per lane
+    constexpr int CH = 16 * LN;          // vectors per chunk
+    // LDS plane: the full 20 x 20 square x in [-6, 14), y in [-6, 14) (corners
+    // unused) so every neighbour is a constant offset from the centre
+    __shared__ V plane[2][400][16];
+    __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][16][4];
 
     // XCD-aware tile order: workgroup ids are dealt round-robin to the 8
     // XCDs; give each XCD a contiguous run of the (chunk-major, Hilbert-
     // ordered) tile sequence so that neighbouring blocks share its L2.
     const int64_t ntiles = n_blocks * n_chunks;
-    const int64_t wg = blockIdx.x;
     const int64_t per_xcd = (ntiles + 7) / 8;
-    const int64_t xcd = wg % 8, idx = wg / 8;
-    const int64_t tile = xcd * per_xcd + idx;
+    const int64_t tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tile >= ntiles) return;
-    const int chunk = int(tile / n_blocks);
-    const int64_t blk = tile - int64_t(chunk) * n_blocks;
 
     const int t = threadIdx.x;
-    const int q = t & 7;                 // quad within the chunk
-    const int col = t >> 3;              // column 0..63
+    const int p = t & 15;                // lane within the chunk
+    const int col = t >> 4;              // column 0..63
     const int cx = col & 7, cy = col >> 3;
-    const int vbase = chunk * CH + q * QN;
-    const bool vok = vbase < nvec;       // nvec is a multiple of QN (host-checked)
-
-    int32_t nbs[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) nbs[f] = bnb[6 * blk + f];
-    uint64_t mymask[8];
-#pragma unroll
-    for (int w = 0; w < 8; ++w) mymask[w] = bmask[8 * blk + w];
-
-    auto inside_local = [&](int l) -> bool { return (mymask[l >> 6] >> (l & 63)) & 1; };
-    auto load_row = [&](int64_t row) -> V {
-        return vok ? *reinterpret_cast<const V*>(X + row * ldx + vbase) : vzero<V>();
+    const int wave = t >> 6;
+    const unsigned es = sizeof(T);
+    const unsigned blk_bytes = unsigned(kBlockPts) * unsigned(ldx) * es;
+    constexpr unsigned kOOB = 0x80000000u;
+    const unsigned plane_x = 64u * unsigned(ldx) * es;
+    const unsigned plane_z = 64u * unsigned(ldz) * es;
+    const unsigned plane_y = 64u * unsigned(ldy) * es;
+    const int ctr = (cy + 6) * 20 + (cx + 6);
+    auto res_x = [&](int32_t nb) {
+        return make_rsrc(nb >= 0 ? X + int64_t(nb) * kBlockPts * ldx : X, nb >= 0 ? blk_bytes : 0u);
     };
 
-    // register window: w[i] = X(cx, cy, z - 6 + i), i = 0..19; rows are
-    // loaded one plane ahead of use so that about 14 are live at a time.
+    struct TileIO {
+        int64_t blk;
+        int chunk;
+        bool vok;
+        unsigned off_x, off_z;
+        int32_t nbs[6];
+        __amdgpu_buffer_rsrc_t rOwn, rZm, rZp, rH[3], rZ;
+        unsigned hoff[3];
+    };
+    TileIO io;
+    io.chunk = int(tile / n_blocks);
+    io.blk = tile - int64_t(io.chunk) * n_blocks;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) io.nbs[f] = bnb[6 * io.blk + f];
+    {
+        const int vbase = io.chunk * CH + p * LN;
+        io.vok = vbase < nvec;
+        io.off_x = io.vok ? (unsigned(cx + 8 * cy) * unsigned(ldx) + unsigned(vbase)) * es : kOOB;
+        io.off_z = io.vok ? (unsigned(cx + 8 * cy) * unsigned(ldz) + unsigned(vbase)) * es : kOOB;
+    }
+    io.rOwn = res_x(int32_t(io.blk));
+    io.rZm = res_x(io.nbs[4]);
+    io.rZp = res_x(io.nbs[5]);
+    io.rZ = make_rsrc(Z ? Z + io.blk * kBlockPts * ldz : X, Z ? unsigned(kBlockPts) * unsigned(ldz) * es : 0u);
+    // Halo slot u of a wave covers 4 consecutive halo rows, all on one side
+    // of the block (48 rows per side), so the side is wave-uniform.
+    int hrow[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int hr0 = 4 * wave + 64 * u;
+        const int side = __builtin_amdgcn_readfirstlane(hr0 / 48);
+        const int hr = (t >> 4) + 64 * u;
+        const int rem = hr - 48 * side;
+        int lx, ly, x, y, nb;
+        if (side < 2) {
+            const int c6 = rem % 6;
+            ly = rem / 6;
+            lx = side == 0 ? 2 + c6 : c6;
+            x = side == 0 ? c6 - 6 : 8 + c6;
+            y = ly;
+            nb = side == 0 ? io.nbs[0] : io.nbs[1];
+        } else {
+            const int r6 = rem / 8;
+            lx = rem % 8;
+            ly = side == 2 ? 2 + r6 : r6;
+            x = lx;
+            y = side == 2 ? r6 - 6 : 8 + r6;
+            nb = side == 2 ? io.nbs[2] : io.nbs[3];
+        }
+        hrow[u] = (y + 6) * 20 + (x + 6);
+        io.rH[u] = res_x(__builtin_amdgcn_readfirstlane(nb));
+        io.hoff[u] = io.vok ? (unsigned(lx + 8 * ly) * unsigned(ldx) + unsigned(io.chunk * CH + p * LN)) * es : kOOB;
+    }
+    auto load_plane = [&](const TileIO& io, int zz) -> V {
+        if (zz < 0) return bload<V>(io.rZm, io.off_x + unsigned(zz + 8) * plane_x);
+        if (zz >= 8) return bload<V>(io.rZp, io.off_x + unsigned(zz - 8) * plane_x);
+        return bload<V>(io.rOwn, io.off_x + unsigned(zz) * plane_x);
+    };
+    auto load_halo = [&](const TileIO& io, int z, V* hv) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) hv[u] = bload<V>(io.rH[u], io.hoff[u] + unsigned(z) * plane_x);
+    };
+    auto store_halo = [&](int b, const V* hv) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) plane[b][hrow[u]][p] = hv[u];
+    };
+    auto load_z = [&](const TileIO& io, int z) -> V { return bload<V>(io.rZ, io.off_z + unsigned(z) * plane_z); };
+
     V w[20];
-    const int64_t base = blk * kBlockPts;
-    auto load_plane = [&](int zz) -> V {
-        if (zz < 0) {
-            if (nbs[4] >= 0) return load_row(int64_t(nbs[4]) * kBlockPts + cx + 8 * cy + 64 * (zz + 8));
-            return vzero<V>();
-        }
-        if (zz >= 8) {
-            if (nbs[5] >= 0) return load_row(int64_t(nbs[5]) * kBlockPts + cx + 8 * cy + 64 * (zz - 8));
-            return vzero<V>();
-        }
-        return load_row(base + cx + 8 * cy + 64 * zz);
-    };
 #pragma unroll
-    for (int i = 0; i < 14; ++i) w[i] = load_plane(i - 6);
-    // Rows outside the sphere hold zeros in every buffer (layout contract),
-    // so halo rows need no mask: a missing neighbour block reads as zero.
+    for (int i = 0; i < 14; ++i) w[i] = load_plane(io, i - 6);
+    V hv0[3], hv[3];
+    load_halo(io, 0, hv0);
+    load_halo(io, 1, hv);
+    V zcur = load_z(io, 0);
 
-    // halo loader for plane z into buffer b: 192 halo rows x 8 quads = 1536
-    // quad loads, 3 per thread.
-    auto load_halo = [&](int z, int b) {
+    {
+        const int vbase = io.chunk * CH + p * LN;
+        const int64_t base = io.blk * kBlockPts;
+        // KB coefficients of this block's atoms: issue the loads now, park
+        // them in LDS after the march
+        int na = 0, a0 = 0;
+        V cstage[4];
+        if (STAGE && ent_off) {
+            a0 = blk_atom_off[io.blk];
+            na = min(blk_atom_off[io.blk + 1] - a0, kMaxBlockAtoms);
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int hidx = t + 512 * u;          // 0..1535
-            const int hq = hidx & 7;
-            const int hr = hidx >> 3;              // 0..191
-            int side = hr / 48;                    // 0:-x 1:+x 2:-y 3:+y
-            int rem = hr % 48;
-            int lx, ly, nbx, x, y;
-            if (side < 2) {
-                // 6 columns x 8 rows of y
-                const int c6 = rem % 6;
-                ly = rem / 6;
-                lx = side == 0 ? 2 + c6 : c6;      // local x in the neighbour block
-                x = side == 0 ? c6 - 6 : 8 + c6;   // x in this block's frame
-                y = ly;
-            } else {
-                const int r6 = rem / 8;
-                lx = rem % 8;
-                ly = side == 2 ? 2 + r6 : r6;
-                x = lx;
-                y = side == 2 ? r6 - 6 : 8 + r6;
+            for (int u = 0; u < 4; ++u) {
+                const int e = t + 1024 * u;       // (atom slot, lm, lane)
+                const int sl = e >> 6, lm = (e >> 4) & 3, lp = e & 15;
+                const int vb = io.chunk * CH + lp * LN;
+                if (sl < na && vb < nvec)
+                    cstage[u] = *reinterpret_cast<const V*>(C + (int64_t(blk_atoms[a0 + sl]) * 4 + lm) * nvec + vb);
+                else
+                    cstage[u] = lz<V>();
             }
-            nbx = nbs[side];
-            V val = vzero<V>();
-            if (nbx >= 0) {
-                const int64_t r = int64_t(nbx) * kBlockPts + lx + 8 * ly + 64 * z;
-                if (chunk * CH + hq * QN < nvec)
-                    val = *reinterpret_cast<const V*>(X + r * ldx + chunk * CH + hq * QN);
-            }
-            plane[b][lds_row(x, y)][hq] = val;
         }
-    };
-
-    load_halo(0, 0);
-    plane[0][lds_row(cx, cy)][q] = w[6];
-    __syncthreads();
-
-    const T* vr = veff + base;
-#pragma unroll
-    for (int z = 0; z < 8; ++z) {
-        const int b = z & 1;
-        if (z < 7) {
-            load_halo(z + 1, b ^ 1);
-            plane[b ^ 1][lds_row(cx, cy)][q] = w[z + 7];
-        }
-        if (z < 6) w[z + 14] = load_plane(z + 8);
-        const int l = cx + 8 * cy + 64 * z;
-        const int64_t row = base + l;
-        V acc = vscale(k.c[0], w[z + 6]);
-#pragma unroll
-        for (int s = 1; s <= 6; ++s) {
-            V sum = vadd(w[z + 6 - s], w[z + 6 + s]);
-            sum = vadd(sum, plane[b][lds_row(cx - s, cy)][q]);
-            sum = vadd(sum, plane[b][lds_row(cx + s, cy)][q]);
-            sum = vadd(sum, plane[b][lds_row(cx, cy - s)][q]);
-            sum = vadd(sum, plane[b][lds_row(cx, cy + s)][q]);
-            acc = vfma(k.c[s], sum, acc);
-        }
-        if (vok && !inside_local(l)) {
-            *reinterpret_cast<V*>(Y + row * ldy + vbase) = vzero<V>();
-        } else if (vok) {
-            const V xc = w[z + 6];
-            acc = vfma(vr[l], xc, acc);
-            const int64_t e0 = ent_off[row], e1 = ent_off[row + 1];
-            for (int64_t en = e0; en < e1; ++en) {
-                const int64_t a = ent_atom[en];
-                const T* bb = ent_beta + 4 * en;
-                const T* ca = C + a * 4 * int64_t(nvec) + vbase;
-                acc = vfma(bb[0], *reinterpret_cast<const V*>(ca), acc);
-                acc = vfma(bb[1], *reinterpret_cast<const V*>(ca + nvec), acc);
-                acc = vfma(bb[2], *reinterpret_cast<const V*>(ca + 2 * nvec), acc);
-                acc = vfma(bb[3], *reinterpret_cast<const V*>(ca + 3 * nvec), acc);
-            }
-            V y = vscale(k.alpha, vfma(-k.shift, xc, acc));
-            if (Z) y = vfma(-k.beta, *reinterpret_cast<const V*>(Z + row * ldz + vbase), y);
-            *reinterpret_cast<V*>(Y + row * ldy + vbase) = y;
-        }
+        store_halo(0, hv0);
+        plane[0][ctr][p] = w[6];
         __syncthreads();
+
+        V r[8];
+        const T* vr = veff ? veff + base : nullptr;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            const int b = z & 1;
+            // stage plane z + 1 (its loads were issued one plane ago), then
+            // issue the loads for planes further ahead
+            if (z < 7) {
+                store_halo(b ^ 1, hv);
+                plane[b ^ 1][ctr][p] = w[z + 7];
+            }
+            if (z < 6) load_halo(io, z + 2, hv);
+            V znext = lz<V>();
+            if (z < 7) znext = load_z(io, z + 1);
+            if (z < 6) w[z + 14] = load_plane(io, z + 8);
+
+            const int l = cx + 8 * cy + 64 * z;
+            V acc = lscale(k.c[0], w[z + 6]);
+#pragma unroll
+            for (int s = 1; s <= 6; ++s) {
+                V sum = ladd(w[z + 6 - s], w[z + 6 + s]);
+                sum = ladd(sum, plane[b][ctr - s][p]);
+                sum = ladd(sum, plane[b][ctr + s][p]);
+                sum = ladd(sum, plane[b][ctr - 20 * s][p]);
+                sum = ladd(sum, plane[b][ctr + 20 * s][p]);
+                acc = lfma(k.c[s], sum, acc);
+            }
+            const V xc = w[z + 6];
+            if (vr) acc = lfma(vr[l], xc, acc);
+            V y = lscale(k.alpha, lfma(-k.shift, xc, acc));
+            if (Z) y = lfma(-k.beta, zcur, y);
+            r[z] = y;
+            zcur = znext;
+            __syncthreads();
+        }
+
+        // park the KB coefficients, then prefetch the next tile while the
+        // scatter of this one runs
+        if (STAGE && ent_off) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = t + 1024 * u;
+                const int sl = e >> 6, lm = (e >> 4) & 3, lp = e & 15;
+                if (sl < kMaxBlockAtoms) cst[sl][lp][lm] = cstage[u];
+            }
+        }
+        const int64_t cur_blk = io.blk;
+        const bool cur_vok = io.vok;
+        if (STAGE) __syncthreads();
+
+        // KB scatter for the 8 rows of this column, in rounds so that the
+        // entry loads of all rows are in flight together
+        if (ent_off && cur_vok) {
+            int e0[8], e1[8];
+            int nmax = 0;
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                const int64_t row = base + cx + 8 * cy + 64 * z;
+                e0[z] = ent_off[row];
+                e1[z] = ent_off[row + 1];
+                nmax = max(nmax, e1[z] - e0[z]);
+            }
+            for (int j = 0; j < nmax; ++j) {
+#pragma unroll
+                for (int z = 0; z < 8; ++z) {
+                    const int en = e0[z] + j;
+                    if (en < e1[z]) {
+                        const T* bb = ent_beta + 4 * int64_t(en);
+                        V c0, c1, c2, c3;
+                        if (STAGE) {
+                            const int sl = ent_slot[en];
+                            c0 = cst[sl][p][0];
+                            c1 = cst[sl][p][1];
+                            c2 = cst[sl][p][2];
+                            c3 = cst[sl][p][3];
+                        } else {
+                            const T* ca = C + int64_t(ent_atom[en]) * 4 * int64_t(nvec) + vbase;
+                            c0 = *reinterpret_cast<const V*>(ca);
+                            c1 = *reinterpret_cast<const V*>(ca + nvec);
+                            c2 = *reinterpret_cast<const V*>(ca + 2 * nvec);
+                            c3 = *reinterpret_cast<const V*>(ca + 3 * nvec);
+                        }
+                        V acc = lscale(bb[0], c0);
+                        acc = lfma(bb[1], c1, acc);
+                        acc = lfma(bb[2], c2, acc);
+                        acc = lfma(bb[3], c3, acc);
+                        r[z] = lfma(k.alpha, acc, r[z]);
+                    }
+                }
+            }
+        }
+        {
+            const __amdgpu_buffer_rsrc_t rY = make_rsrc(Y + base * ldy, unsigned(kBlockPts) * unsigned(ldy) * es);
+            const unsigned off_y = cur_vok ? (unsigned(cx + 8 * cy) * unsigned(ldy) + unsigned(vbase)) * es : kOOB;
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                const bool in = (bmask[8 * cur_blk + z] >> (cx + 8 * cy)) & 1;
+                bstore<V>(in ? r[z] : lz<V>(), rY, off_y + unsigned(z) * plane_y);
+            }
+        }
     }
 }
 
 template <class T>
 void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
-                     const T* C, double alpha, double shift, double beta, hipStream_t s) {
-    constexpr int CH = 8 * Quad<T>::N;
+                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only) {
+    constexpr int CH = 16 * Lane<T>::N;
     const int n_chunks = (nvec + CH - 1) / CH;
     const int64_t nt = H->grid.n_blocks * n_chunks;
     const int64_t nwg = ((nt + 7) / 8) * 8;
-    hx_tiled_kernel<T><<<dim3(unsigned(nwg)), dim3(512), 0, s>>>(
-        H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff_of<T>(H),
-        H->ent_off.as<int64_t>(), H->ent_atom.as<int32_t>(), ent_beta_of<T>(H), C, nvec, X, ldx, Y, ldy, Z, ldz,
-        make_coef<T>(H, alpha, shift, beta));
+    const bool kb = !lap_only && H->proj.n_proj > 0;
+    const bool stage = kb && H->proj.max_block_atoms <= kMaxBlockAtoms;
+    const int32_t* eo = kb ? H->ent_off32.as<int32_t>() : nullptr;
+    const StepCoef<T> coef = make_coef<T>(H, alpha, shift, beta);
+    const T* veff = lap_only ? nullptr : veff_of<T>(H);
+    if (stage)
+        hx_tiled_kernel<T, true><<<dim3(unsigned(nwg)), dim3(1024), 0, s>>>(
+            H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,
+            H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),
+            H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef);
+    else
+        hx_tiled_kernel<T, false><<<dim3(unsigned(nwg)), dim3(1024), 0, s>>>(
+            H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,
+            H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),
+            H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef);
     LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// optional per-kernel timing: HIP events recorded on the launch stream
+// around every H X and KB-gather launch while enabled
+// ---------------------------------------------------------------------------
+struct KernelTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[2];   // 0: H X, 1: KB gather
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreate(&e));
+        return e;
+    }
+    void recycle() {
+        for (auto& v : spans) {
+            for (auto& p : v) {
+                pool.push_back(p.first);
+                pool.push_back(p.second);
+            }
+            v.clear();
+        }
+    }
+};
+static KernelTimer g_timer;
+
+template <class F>
+static void timed(int which, hipStream_t s, F&& launch) {
+    if (!g_timer.on) {
+        launch();
+        return;
+    }
+    hipEvent_t a = g_timer.get(), b = g_timer.get();
+    HIP_CHECK(hipEventRecord(a, s));
+    launch();
+    HIP_CHECK(hipEventRecord(b, s));
+    g_timer.spans[which].emplace_back(a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -465,33 +735,53 @@ void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, con
 template <class T>
 bool tiled_ok(const chf_ham* H, const void* X, int64_t ldx, const void* Y, int64_t ldy, const void* Z, int64_t ldz,
               int nvec) {
-    constexpr int QN = Quad<T>::N;
+    constexpr int LN = Lane<T>::N;
     if (H->grid.ordering != CHF_ORDER_HILBERT) return false;
-    if (nvec % QN || ldx % QN || ldy % QN || (Z && ldz % QN)) return false;
-    const uintptr_t al = 16;
+    if (nvec % LN || ldx % LN || ldy % LN || (Z && ldz % LN)) return false;
+    if (int64_t(kBlockPts) * std::max(ldx, std::max(ldy, ldz)) * int64_t(sizeof(T)) >= (int64_t(1) << 30)) return false;
+    const uintptr_t al = 8;
     if (uintptr_t(X) % al || uintptr_t(Y) % al || (Z && uintptr_t(Z) % al)) return false;
     return true;
 }
 
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel) {
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only) {
     H->kb_coef.ensure(size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * sizeof(T));
     T* C = H->kb_coef.as<T>();
-    launch_kb_gather<T>(H, X, ldx, nvec, C, s);
+    if (H->proj.n_proj > 0 && !lap_only) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, C, s); });
     const bool tiled = force_kernel != 1 && tiled_ok<T>(H, X, ldx, Y, ldy, Z, ldz, nvec);
     if (tiled) {
-        launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s);
+        timed(0, s, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
     } else {
         if (!H->has_nbr) fail(CHF_EUNSUPPORTED, "generic H X needs the neighbour table (keep_nbr) for this layout");
-        launch_hx_generic<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s);
+        timed(0, s, [&] { launch_hx_generic<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
+    }
+}
+
+void timer_enable(int on) {
+    g_timer.recycle();
+    g_timer.on = on != 0;
+}
+
+void timer_read(double* ms, int64_t* launches) {
+    HIP_CHECK(hipDeviceSynchronize());
+    for (int w = 0; w < 2; ++w) {
+        double t = 0;
+        for (auto& p : g_timer.spans[w]) {
+            float f = 0;
+            HIP_CHECK(hipEventElapsedTime(&f, p.first, p.second));
+            t += f;
+        }
+        ms[w] = t;
+        launches[w] = int64_t(g_timer.spans[w].size());
     }
 }
 
 template void hx_step<float>(chf_ham*, const float*, int64_t, float*, int64_t, const float*, int64_t, int, double,
-                             double, double, hipStream_t, int);
+                             double, double, hipStream_t, int, bool);
 template void hx_step<double>(chf_ham*, const double*, int64_t, double*, int64_t, const double*, int64_t, int,
-                              double, double, double, hipStream_t, int);
+                              double, double, double, hipStream_t, int, bool);
 template void launch_kb_gather<float>(chf_ham*, const float*, int64_t, int, float*, hipStream_t);
 template void launch_kb_gather<double>(chf_ham*, const double*, int64_t, int, double*, hipStream_t);
 

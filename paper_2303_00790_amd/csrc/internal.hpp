@@ -132,20 +132,21 @@ struct HostProj {
     std::vector<int64_t> ent_off;       // [n_rows + 1]
     std::vector<int32_t> ent_atom;      // [pairs] projector-atom index
     std::vector<double> ent_beta;       // [pairs][4]
+    // blockwise view (Hilbert layout): atoms touching each 8^3 block and the
+    // slot of every row entry's atom in its block's list
+    std::vector<int64_t> blk_atom_off;  // [n_blocks + 1]
+    std::vector<int32_t> blk_atoms;     // projector-atom indices, ascending per block
+    std::vector<uint8_t> ent_slot;      // [pairs]
+    int max_block_atoms = 0;
 };
+
+void build_block_atoms(const HostGrid& g, HostProj& P);
 
 void build_projectors(const HostGrid& g, const chf_atoms& atoms, const chf_pp& pp, HostProj& out);
 
 // ---------------------------------------------------------------------------
 // device-side objects
 // ---------------------------------------------------------------------------
-struct ProjTables {        // one precision
-    DevBuf sup_row;        // int32 [pairs]  (shared across precisions; owned by F64/F32 alike)
-    DevBuf sup_beta;       // T [pairs][4], scaled by h^3
-    DevBuf ent_atom;       // int32 [pairs]
-    DevBuf ent_beta;       // T [pairs][4], scaled by h_l
-};
-
 }  // namespace chf
 
 struct chf_ham {
@@ -165,8 +166,12 @@ struct chf_ham {
     chf::DevBuf veff32;         // float  [n_rows]
     chf::DevBuf sup_off;        // int64 [n_proj + 1]
     chf::DevBuf sup_row;        // int32 [pairs]
-    chf::DevBuf ent_off;        // int64 [n_rows + 1]  (int32 when it fits: see ent_off32)
+    chf::DevBuf ent_off;        // int64 [n_rows + 1]
+    chf::DevBuf ent_off32;      // int32 [n_rows + 1] (pairs < 2^31)
     chf::DevBuf ent_atom;       // int32 [pairs]
+    chf::DevBuf ent_slot;       // uint8 [pairs] slot of the entry's atom in its block list
+    chf::DevBuf blk_atom_off;   // int32 [n_blocks + 1]
+    chf::DevBuf blk_atoms;      // int32 [sum of block atom counts]
     chf::DevBuf sup_beta64, ent_beta64;  // double [pairs][4]
     chf::DevBuf sup_beta32, ent_beta32;  // float  [pairs][4]
     chf::DevBuf kb_coef;        // KB coefficients scratch [4 n_proj][nvec] in the work dtype

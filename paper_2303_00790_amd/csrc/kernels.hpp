@@ -9,12 +9,29 @@ void launch_cast_veff(chf_ham* H, const double* src, double* d64, float* d32, in
 template <class T>
 void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipStream_t s);
 // Y = alpha (H X - shift X) - beta Z ; Z may be null or alias Y.  force_kernel:
-// 0 = best available, 1 = generic neighbour-table kernel.
+// 0 = best available, 1 = generic neighbour-table kernel.  lap_only: H is
+// replaced by -1/2 L (no V_eff, no projectors).
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel);
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false);
+
+void timer_enable(int on);
+void timer_read(double* ms, int64_t* launches);
 
 // dense.hip
+template <class T>
+void dot_device(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, int64_t incy, double* out_dev,
+                hipStream_t s);
+template <class T>
+double dot_host(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, int64_t incy, hipStream_t s);
+void lincomb(int64_t n, double a, const double* x, int64_t incx, double b, const double* y, int64_t incy, double* z,
+             int64_t incz, hipStream_t s);
+template <class T>
+void orthonormalize_t(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, int* fallbacks, hipStream_t s);
+template <class T>
+void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double* eig_host, T* W, int64_t ldw,
+                     hipStream_t s);
+void lanczos_run(chf_ham* H, chf_ctx* ctx, const double* v0, int k, double* out3, hipStream_t s);
 template <class T>
 void gram_product(chf_ctx* ctx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n_rows, int m, int n,
                   double* S, int64_t lds, hipStream_t s);

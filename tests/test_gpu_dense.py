@@ -1,0 +1,132 @@
+"""GPU parity of the dense ChFSI steps (MFMA Gram products, Lanczos bound,
+Cholesky-QR, Rayleigh-Ritz, one full ChFSI iteration) against the FP64
+oracle, through the C ABI.
+
+Tolerances: FP64 Gram 1e-13 relative (the products are exact dot products in
+a different summation order); FP32 Gram 2e-6 relative to |A||B| (FP32
+accumulation over at most 2048 rows, eps_32 * sqrt(2048) ~ 3e-6 worst-case
+random-walk, partials added in FP64).  Eigenvalues from FP64 paths 1e-10 Ha.
+"""
+import numpy as np
+import pytest
+
+from oracle import chfsi as OC
+from synth.cluster import random_block
+
+from gpu_system import build, from_rows, relerr, to_rows
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def system():
+    s = build()
+    s["ctx"] = s["B"].Context(0)
+    return s
+
+
+@pytest.mark.parametrize("n,m,k,same", [(5003, 70, 45, False), (4000, 130, 130, True), (100000, 64, 64, True),
+                                        (300, 17, 3, False)])
+def test_gram_f64(system, n, m, k, same):
+    B = system["B"]
+    rng = np.random.default_rng(n + m)
+    A = rng.standard_normal((n, m))
+    Bm = A if same else rng.standard_normal((n, k))
+    At = torch.from_numpy(A).cuda()
+    Bt = At if same else torch.from_numpy(Bm).cuda()
+    S = torch.zeros((m, Bm.shape[1]), dtype=torch.float64, device="cuda")
+    B.gram(system["ctx"], At, Bt, S)
+    assert relerr(S.cpu().numpy(), A.T @ Bm) < 1e-13
+
+
+@pytest.mark.parametrize("n,m", [(70000, 96), (5000, 33)])
+def test_gram_f32(system, n, m):
+    B = system["B"]
+    rng = np.random.default_rng(5)
+    A32 = rng.standard_normal((n, m)).astype(np.float32)
+    At = torch.from_numpy(A32).cuda()
+    S = torch.zeros((m, m), dtype=torch.float64, device="cuda")
+    B.gram(system["ctx"], At, At, S)
+    ref = A32.astype(np.float64).T @ A32.astype(np.float64)
+    assert float(np.abs(S.cpu().numpy() - ref).max() / n) < 2e-6
+    assert np.array_equal(S.cpu().numpy(), S.cpu().numpy().T)
+
+
+def test_lanczos_bound(system):
+    s = system
+    v0 = random_block(s["g"].n, 1, 3001)[:, 0]
+    ref = OC.lanczos_bound(s["Ho"].apply, v0, 10)
+    got = s["Hg"].lanczos_bound(s["ctx"], to_rows(s, v0, torch.float64), 10)
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_orthonormalize_f64(system):
+    s = system
+    X = random_block(s["g"].n, 96, 2400)
+    Q, R = OC.cholesky_qr(X)
+    Xg = to_rows(s, X, torch.float64)
+    fb = s["B"].orthonormalize(s["ctx"], Xg)
+    assert fb == 0
+    assert relerr(from_rows(s, Xg, 96), Q) < 1e-11
+    G = (Xg.T @ Xg).cpu().numpy()
+    assert np.abs(G - np.eye(96)).max() < 1e-12
+    pad = torch.ones(s["Hg"].n_rows, dtype=torch.bool, device="cuda")
+    pad[s["rows"]] = False
+    assert float(Xg[pad].abs().max()) == 0.0
+
+
+def test_orthonormalize_f32(system):
+    s = system
+    X = random_block(s["g"].n, 64, 2401)
+    Xg = to_rows(s, X, torch.float32)
+    s["B"].orthonormalize(s["ctx"], Xg)
+    G = (Xg.double().T @ Xg.double()).cpu().numpy()
+    assert np.abs(G - np.eye(64)).max() < 5e-5
+
+
+def test_orthonormalize_rank_deficient_falls_back(system):
+    s = system
+    X = random_block(s["g"].n, 32, 2402)
+    X[:, 5] = X[:, 4]                     # exactly dependent columns
+    Xg = to_rows(s, X, torch.float64)
+    try:
+        fb = s["B"].orthonormalize(s["ctx"], Xg)
+        assert fb == 1
+    except s["B"].ChfError as e:
+        assert e.code == -4
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
+def test_rayleigh_ritz(system, dtype, tol):
+    s = system
+    X, _ = OC.cholesky_qr(random_block(s["g"].n, 64, 2403))
+    lam, Xr = OC.rayleigh_ritz(s["Ho"].apply, X)
+    Xg = to_rows(s, X, dtype)
+    W = torch.zeros_like(Xg)
+    eig = s["B"].rayleigh_ritz(s["Hg"], s["ctx"], Xg, W)
+    assert np.abs(eig - lam).max() < tol * max(1.0, np.abs(lam).max())
+    if dtype == torch.float64:
+        got = from_rows(s, Xg, 64)
+        sign = np.sign((got * Xr).sum(0))
+        gaps = np.minimum(np.diff(lam, prepend=-np.inf), np.diff(lam, append=np.inf))
+        ok = gaps > 1e-6
+        assert relerr((got * sign)[:, ok], Xr[:, ok]) < 1e-8
+
+
+def test_chfsi_iteration_f64(system):
+    s = system
+    X = random_block(s["g"].n, 64, 2404)
+    v0 = random_block(s["g"].n, 1, 3001)[:, 0]
+    b, tmin, _ = OC.lanczos_bound(s["Ho"].apply, v0)
+    a0, a = tmin, tmin + 0.1 * (b - tmin)
+    Xo = X
+    Xg = to_rows(s, X, torch.float64)
+    W = torch.zeros_like(Xg)
+    for _ in range(3):
+        lam, Xo = OC.chfsi_iteration(s["Ho"].apply, Xo, 10, a, b, a0)
+        s["Hg"].filter(Xg, W, 10, a, b, a0)
+        s["B"].orthonormalize(s["ctx"], Xg)
+        eig = s["B"].rayleigh_ritz(s["Hg"], s["ctx"], Xg, W)
+        assert np.abs(eig - lam).max() < 1e-9
+        a, a0 = lam[-1], lam[0]
