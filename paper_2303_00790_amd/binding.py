@@ -353,8 +353,9 @@ class Scf:
         call("scf_step", self.handle, px, ldx, pw, ldw, C.byref(rep), P(eig.ctypes.data))
         return rep, eig
 
-    def fields(self, rho_in, vh):
-        call("chf_scf_get_fields", self.handle, _ptr(rho_in), _ptr(vh))
+    def fields(self, rho_in, vh=None):
+        call("chf_scf_get_fields", self.handle, _ptr(rho_in) if rho_in is not None else None,
+             _ptr(vh) if vh is not None else None)
 
     def close(self):
         if self.handle:

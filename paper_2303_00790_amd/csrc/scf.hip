@@ -587,7 +587,7 @@ static void anderson_mix(chf_scf* S, hipStream_t s) {
         for (int j = 0; j < m; ++j) rhs[j] = hs[t++];
         solve_small(G, rhs, m, gam);
     }
-    HIP_CHECK(hipMemcpyAsync(gdev, gam.data(), size_t(std::max(1, m)) * sizeof(double), hipMemcpyHostToDevice, s));
+    if (m > 0) HIP_CHECK(hipMemcpyAsync(gdev, gam.data(), size_t(m) * sizeof(double), hipMemcpyHostToDevice, s));
     double* tmp = S->f(F_TMP);
     anderson_mix_kernel<<<nblk(n), 256, 0, s>>>(n, m, gdev, S->prm.mix_beta, x, f, S->hx(0), S->hf(0), n, tmp);
     LAUNCH_CHECK();

@@ -109,5 +109,8 @@ def test_scf_steps_fp64(si35):
         assert abs(rep.energy - r.energy) < 1e-8, (k, rep.energy, r.energy)
         assert abs(rep.sre_ry - r.sre_ry) < 1e-6 * r.sre_ry
         assert abs(rep.homo - r.homo) < 1e-8 and abs(rep.lumo - r.lumo) < 1e-8
+    # the mixed density kept by the state equals the oracle's
     rho_in = torch.zeros(s["Hg"].n_rows, dtype=torch.float64, device="cuda")
-    scf.fields(rho_in, None) if False else None
+    vh = torch.zeros_like(rho_in)
+    scf.fields(rho_in, vh)
+    assert relerr(from_rows(s, rho_in), st.rho_in) < 1e-8
