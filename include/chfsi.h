@@ -239,6 +239,10 @@ int chf_lda(chf_ham* ham, const double* rho_dev, double* exc_dev, double* vxc_de
 int chf_sad_density(chf_ham* ham, const chf_atoms* atoms, double alpha_si, double alpha_h, int n_electrons,
                     double* rho_dev, void* stream);
 
+/* Clamps rho_dev (FP64 [n_rows]) at zero and rescales it to h^3 sum rho =
+ * n_electrons (used on a learned start density). */
+int chf_density_fix(chf_ham* ham, double* rho_dev, int n_electrons, void* stream);
+
 /* Ion-ion energy sum_{a < b} Z_a Z_b / |R_a - R_b| (host, Ha). */
 int chf_ion_energy(const chf_atoms* atoms, const chf_pp* pp, double* out_host);
 
@@ -286,6 +290,54 @@ int scf_step(chf_scf* scf, void* X_dev, int64_t ldx, void* work_dev, int64_t ldw
 /* Checkpoint access: copy rho_in / V_H ([n_rows] FP64) out of or into the
  * state (device to device, on the SCF's stream). */
 int chf_scf_get_fields(chf_scf* scf, double* rho_in_dev, double* vh_dev);
+
+/* ---------------------------------------------------------------------------
+ * Learned initial density: a 3-D U-Net (4 levels, `channels` channels, two
+ * 3^3 conv + SiLU per level, stride-2 conv down, nearest upsample + 3^3 conv
+ * up, skip concatenation, final 1^3 conv) mapping a scaled superposition-of-
+ * atoms density on an S^3 patch to a scaled correction.  BF16 MFMA
+ * convolutions with FP32 accumulation; FP32 master weights and Adam state.
+ * Not in the paper: the method's extension that starts the SCF from a
+ * corrected density; the plain superposition start remains the fallback.
+ * ------------------------------------------------------------------------- */
+typedef struct dnet dnet;
+
+/* He-normal initialisation from `seed`; the output layer starts at zero. */
+int dnet_create(int channels, uint64_t seed, dnet** out);
+int dnet_destroy(dnet* net);
+/* Number of FP32 master parameters (padded layout, see dnet_layer_info). */
+int dnet_param_count(const dnet* net, int64_t* n);
+/* Layer `layer` (0..20, in the order c1a c1b d1 c2a c2b d2 c3a c3b d3 c4a c4b
+ * u3 c5a c5b u2 c6a c6b u1 c7a c7b out): info6 = {c_in, c_out, c_in padded,
+ * c_out padded, kernel edge, stride}; offsets2 = {weight offset, bias
+ * offset}.  Weights are [c_out padded][tap][c_in padded], tap = (dz*3+dy)*3+dx. */
+int dnet_layer_info(const dnet* net, int layer, int* info6, int64_t* offsets2);
+int dnet_get_params(const dnet* net, float* host);
+int dnet_set_params(dnet* net, const float* host);
+int dnet_get_grads(const dnet* net, float* host);
+/* y_dev [S^3] = net(x_dev [S^3]) (x-fastest); keeps the activations for
+ * dnet_backward.  S a multiple of 8 in [8, 512]. */
+int dnet_forward(dnet* net, const float* x_dev, int S, float* y_dev, void* stream);
+/* Accumulates parameter gradients of the last forward for dL/dy = dy_dev. */
+int dnet_backward(dnet* net, const float* dy_dev, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected; step >= 1),
+ * then clears the gradients. */
+int dnet_adam(dnet* net, float lr, int step, void* stream);
+/* Mean squared error of y against t (n values) into *loss_host, and
+ * dL/dy = 2 (y - t) / n into dy_dev (may be NULL). */
+int dnet_mse(dnet* net, const float* y_dev, const float* t_dev, int64_t n, double* loss_host, float* dy_dev,
+             void* stream);
+/* patch [S^3] = box [D^3] read at offset (ox, oy, oz) under cubic symmetry
+ * sym in [0, 48) (axis permutation sym / 8, mirrored axes bits sym % 8);
+ * cells outside the box read 0. */
+int dnet_crop(const float* box_dev, int D, int S, int ox, int oy, int oz, int sym, float* patch_dev, void* stream);
+
+/* Grid rows <-> cubic box of edge D (x-fastest) holding grid point (i, j, k)
+ * at (i + off, j + off, k + off): box = scale * rows (cells without a grid
+ * point 0); rows_out = base_rows + box / scale on inside rows (padding 0). */
+int chf_rows_to_box(chf_ham* ham, const double* rows_dev, double scale, float* box_dev, int D, int off, void* stream);
+int chf_box_to_rows(chf_ham* ham, const float* box_dev, int D, int off, double scale, const double* base_rows_dev,
+                    double* rows_out_dev, void* stream);
 
 #ifdef __cplusplus
 }

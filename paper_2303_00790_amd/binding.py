@@ -89,10 +89,25 @@ _SIGS = {
     "chf_lda": [P, P, P, P, P],
     "chf_sad_density": [P, C.POINTER(Atoms), D, D, INT, P, P],
     "chf_ion_energy": [C.POINTER(Atoms), C.POINTER(PP), C.POINTER(D)],
+    "chf_density_fix": [P, P, INT, P],
     "chf_scf_create": [P, P, C.POINTER(ScfParams), P, P, C.POINTER(P)],
     "chf_scf_destroy": [P],
     "scf_step": [P, P, I64, P, I64, C.POINTER(ScfReport), P],
     "chf_scf_get_fields": [P, P, P],
+    "dnet_create": [INT, C.c_uint64, C.POINTER(P)],
+    "dnet_destroy": [P],
+    "dnet_param_count": [P, C.POINTER(I64)],
+    "dnet_layer_info": [P, INT, P, P],
+    "dnet_get_params": [P, P],
+    "dnet_set_params": [P, P],
+    "dnet_get_grads": [P, P],
+    "dnet_forward": [P, P, INT, P, P],
+    "dnet_backward": [P, P, P],
+    "dnet_adam": [P, C.c_float, INT, P],
+    "dnet_mse": [P, P, P, I64, C.POINTER(D), P, P],
+    "dnet_crop": [P, INT, INT, INT, INT, INT, INT, P, P],
+    "chf_rows_to_box": [P, P, D, P, INT, INT, P],
+    "chf_box_to_rows": [P, P, INT, INT, D, P, P, P],
 }
 
 _lib = None
@@ -296,6 +311,9 @@ class Hamiltonian:
     def lda(self, rho, exc, vxc):
         call("chf_lda", self.handle, _ptr(rho), _ptr(exc) if exc is not None else None, _ptr(vxc), _stream())
 
+    def density_fix(self, rho, n_electrons: int):
+        call("chf_density_fix", self.handle, _ptr(rho), n_electrons, _stream())
+
     def sad_density(self, pos, species, n_electrons: int, alpha_si: float = 0.074, alpha_h: float = 0.21):
         import torch
         a, keep = _atoms(pos, species)
@@ -367,3 +385,77 @@ class Scf:
             self.close()
         except Exception:
             pass
+
+
+LAYER_NAMES = ["c1a", "c1b", "d1", "c2a", "c2b", "d2", "c3a", "c3b", "d3", "c4a", "c4b", "u3", "c5a", "c5b", "u2",
+               "c6a", "c6b", "u1", "c7a", "c7b", "out"]
+
+
+class DensityNet:
+    """Device U-Net for the initial-density correction (dnet_* calls)."""
+
+    def __init__(self, channels: int = 32, seed: int = 0):
+        self.handle = P()
+        call("dnet_create", channels, seed, C.byref(self.handle))
+        n = I64()
+        call("dnet_param_count", self.handle, C.byref(n))
+        self.n_params = n.value
+        self.layers = {}
+        for i, name in enumerate(LAYER_NAMES):
+            info = (C.c_int * 6)()
+            off = (C.c_int64 * 2)()
+            call("dnet_layer_info", self.handle, i, C.cast(info, P), C.cast(off, P))
+            self.layers[name] = (tuple(info), tuple(off))
+
+    def close(self):
+        if self.handle:
+            call("dnet_destroy", self.handle)
+            self.handle = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        call("dnet_get_params", self.handle, P(out.ctypes.data))
+        return out
+
+    def set_params(self, flat: np.ndarray) -> None:
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        call("dnet_set_params", self.handle, P(flat.ctypes.data))
+
+    def get_grads(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        call("dnet_get_grads", self.handle, P(out.ctypes.data))
+        return out
+
+    def forward(self, x, y):
+        call("dnet_forward", self.handle, _ptr(x), int(round(x.numel() ** (1 / 3))), _ptr(y), _stream())
+
+    def backward(self, dy):
+        call("dnet_backward", self.handle, _ptr(dy), _stream())
+
+    def adam(self, lr: float, step: int):
+        call("dnet_adam", self.handle, lr, step, _stream())
+
+    def mse(self, y, t, dy=None) -> float:
+        loss = C.c_double()
+        call("dnet_mse", self.handle, _ptr(y), _ptr(t), y.numel(), C.byref(loss), _ptr(dy) if dy is not None else None,
+             _stream())
+        return loss.value
+
+
+def crop(box, D: int, S: int, origin, sym: int, patch) -> None:
+    call("dnet_crop", _ptr(box), D, S, int(origin[0]), int(origin[1]), int(origin[2]), sym, _ptr(patch), _stream())
+
+
+def rows_to_box(H: "Hamiltonian", rows, scale: float, box, D: int, off: int) -> None:
+    call("chf_rows_to_box", H.handle, _ptr(rows), scale, _ptr(box), D, off, _stream())
+
+
+def box_to_rows(H: "Hamiltonian", box, D: int, off: int, scale: float, base, out) -> None:
+    call("chf_box_to_rows", H.handle, _ptr(box), D, off, scale, _ptr(base) if base is not None else None, _ptr(out),
+         _stream())

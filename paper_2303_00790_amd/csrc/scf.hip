@@ -301,6 +301,11 @@ __global__ void __launch_bounds__(256) sum_partial_kernel(int64_t n, const doubl
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+__global__ void clamp_kernel(int64_t n, double* __restrict__ v) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && !(v[i] > 0.0)) v[i] = 0.0;
+}
+
 __global__ void scale_kernel(int64_t n, double a, double* __restrict__ v) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) v[i] *= a;
@@ -793,6 +798,31 @@ int chf_sad_density(chf_ham* H, const chf_atoms* atoms, double alpha_si, double 
         HIP_CHECK(hipStreamSynchronize(s));
         const double h3 = H->h * H->h * H->h;
         if (!(tot > 0)) fail(CHF_ENONFINITE, "chf_sad_density: zero density");
+        scale_kernel<<<nblk(n), 256, 0, s>>>(n, n_electrons / (h3 * tot), rho);
+        LAUNCH_CHECK();
+        HIP_CHECK(hipStreamSynchronize(s));
+    });
+}
+
+int chf_density_fix(chf_ham* H, double* rho, int n_electrons, void* stream) {
+    return scf_guard([&] {
+        if (!H || !rho || n_electrons < 1) fail(CHF_EINVAL, "chf_density_fix: bad argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t n = H->grid.n_rows;
+        clamp_kernel<<<nblk(n), 256, 0, s>>>(n, rho);
+        LAUNCH_CHECK();
+        const int nbk = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)));
+        DevBuf part, out;
+        part.alloc(size_t(nbk) * sizeof(double));
+        out.alloc(64);
+        sum_partial_kernel<<<nbk, 256, 0, s>>>(n, rho, part.as<double>());
+        sum_kernel<<<1, 256, 0, s>>>(nbk, part.as<double>(), out.as<double>());
+        LAUNCH_CHECK();
+        double tot = 0;
+        HIP_CHECK(hipMemcpyAsync(&tot, out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        const double h3 = H->h * H->h * H->h;
+        if (!(tot > 0)) fail(CHF_ENONFINITE, "chf_density_fix: density vanishes");
         scale_kernel<<<nblk(n), 256, 0, s>>>(n, n_electrons / (h3 * tot), rho);
         LAUNCH_CHECK();
         HIP_CHECK(hipStreamSynchronize(s));

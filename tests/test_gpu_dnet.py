@@ -1,0 +1,132 @@
+"""GPU parity of the density network against the FP64 oracle.
+
+The device runs BF16 weights and activations into MFMA with FP32
+accumulation; the oracle runs FP64 on the same BF16-rounded weights and
+input.  Between layers the device rounds activations to BF16 (relative
+2^-8 per layer, ~21 layers), so forward outputs and gradients are compared
+at 3e-2 relative to their largest magnitude; the Adam update is compared
+exactly (same FP32 gradients on both sides, 1e-5).
+"""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    a32 = np.asarray(a, np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def to_oracle(net, flat):
+    p = {}
+    for name, (info, off) in net.layers.items():
+        cin, cout, cin_p, cout_p, k, _ = info
+        ntap = k ** 3
+        w = flat[off[0]:off[0] + cout_p * ntap * cin_p].reshape(cout_p, ntap, cin_p)[:cout, :, :cin]
+        p[name + ".w"] = w.transpose(0, 2, 1).reshape(cout, cin, k, k, k).astype(np.float64)
+        p[name + ".b"] = flat[off[1]:off[1] + cout].astype(np.float64)
+    return p
+
+
+def from_oracle_grad(net, g):
+    flat = np.zeros(net.n_params, np.float64)
+    for name, (info, off) in net.layers.items():
+        cin, cout, cin_p, cout_p, k, _ = info
+        ntap = k ** 3
+        w = np.zeros((cout_p, ntap, cin_p))
+        w[:cout, :, :cin] = g[name + ".w"].reshape(cout, cin, ntap).transpose(0, 2, 1)
+        flat[off[0]:off[0] + w.size] = w.ravel()
+        flat[off[1]:off[1] + cout] = g[name + ".b"]
+    return flat
+
+
+@pytest.fixture(scope="module")
+def net_case():
+    from paper_2303_00790_amd import binding as B
+    C, S = 8, 16
+    net = B.DensityNet(C, seed=3)
+    flat = net.get_params()
+    rng = np.random.default_rng(9)
+    info, off = net.layers["out"]
+    flat[off[0]:off[0] + info[2] * 1] = rng.standard_normal(info[2]).astype(np.float32) * 0.3   # row 0 of out.w
+    flat[off[1]] = 0.1
+    # store BF16-exact master weights so both sides see identical values
+    flat = bf16_round(flat).astype(np.float32)
+    net.set_params(flat)
+    x = bf16_round(np.abs(rng.standard_normal((S, S, S))) + 0.2)
+    t = rng.standard_normal((S, S, S)) * 0.1
+    return B, net, flat, x, t, S
+
+
+def test_forward_and_gradients(net_case):
+    B, net, flat, x, t, S = net_case
+    p = to_oracle(net, flat)
+    y_ref, tape = U.forward(p, x[None], keep=True)
+    loss_ref, dy_ref = U.mse(y_ref, t[None])
+    g_ref = from_oracle_grad(net, U.backward(p, tape, dy_ref))
+    xg = torch.from_numpy(x.astype(np.float32)).cuda()
+    tg = torch.from_numpy(t.astype(np.float32)).cuda()
+    yg = torch.zeros_like(xg)
+    dy = torch.zeros_like(xg)
+    net.forward(xg, yg)
+    loss = net.mse(yg, tg, dy)
+    net.backward(dy)
+    y = yg.cpu().numpy()
+    assert np.abs(y - y_ref[0]).max() < 3e-2 * np.abs(y_ref).max()
+    assert abs(loss - loss_ref) < 3e-2 * loss_ref
+    g = net.get_grads().astype(np.float64)
+    for name, (info, off) in net.layers.items():
+        cin, cout, cin_p, cout_p, k, _ = info
+        sl = slice(off[0], off[0] + cout_p * k ** 3 * cin_p)
+        ref = g_ref[sl]
+        assert np.abs(g[sl] - ref).max() < 3e-2 * np.abs(ref).max() + 1e-12, name
+        bs = slice(off[1], off[1] + cout)
+        assert np.abs(g[bs] - g_ref[bs]).max() < 3e-2 * np.abs(g_ref[bs]).max() + 1e-12, name
+
+
+def test_adam_matches_oracle(net_case):
+    B, net, flat, x, t, S = net_case
+    w0 = net.get_params().astype(np.float64)
+    g = net.get_grads().astype(np.float64)
+    net.adam(1e-3, 1)
+    w1 = net.get_params().astype(np.float64)
+    pd, gd = {"w": w0.copy()}, {"w": g}
+    U.adam_step(pd, gd, {"w": np.zeros_like(w0)}, {"w": np.zeros_like(w0)}, 1, lr=1e-3)
+    assert np.abs(w1 - pd["w"]).max() < 1e-5
+    assert not net.get_grads().any()
+
+
+def test_training_reduces_loss(net_case):
+    B, net, flat, x, t, S = net_case
+    xg = torch.from_numpy(x.astype(np.float32)).cuda()
+    tg = torch.from_numpy((0.05 * x).astype(np.float32)).cuda()
+    yg = torch.zeros_like(xg)
+    dy = torch.zeros_like(xg)
+    losses = []
+    for step in range(1, 31):
+        net.forward(xg, yg)
+        losses.append(net.mse(yg, tg, dy))
+        net.backward(dy)
+        net.adam(3e-3, step)
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_crop_symmetries():
+    from paper_2303_00790_amd import binding as B
+    D, S = 10, 4
+    box = torch.arange(D ** 3, dtype=torch.float32, device="cuda")
+    seen = set()
+    for sym in range(48):
+        patch = torch.zeros(S ** 3, dtype=torch.float32, device="cuda")
+        B.crop(box, D, S, (2, 3, 1), sym, patch)
+        vals = patch.cpu().numpy().reshape(S, S, S)
+        ref = box.cpu().numpy().reshape(D, D, D)[1:1 + S, 3:3 + S, 2:2 + S]
+        assert sorted(vals.ravel()) == sorted(ref.ravel())
+        seen.add(vals.tobytes())
+    assert len(seen) == 48
