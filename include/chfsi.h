@@ -312,6 +312,8 @@ int dnet_param_count(const dnet* net, int64_t* n);
  * c_out padded, kernel edge, stride}; offsets2 = {weight offset, bias
  * offset}.  Weights are [c_out padded][tap][c_in padded], tap = (dz*3+dy)*3+dx. */
 int dnet_layer_info(const dnet* net, int layer, int* info6, int64_t* offsets2);
+/* Host only: output edge of each of the 21 layers for patch edge S. */
+int dnet_plan(int S, int* edges_host);
 int dnet_get_params(const dnet* net, float* host);
 int dnet_set_params(dnet* net, const float* host);
 int dnet_get_grads(const dnet* net, float* host);

@@ -98,6 +98,7 @@ _SIGS = {
     "dnet_destroy": [P],
     "dnet_param_count": [P, C.POINTER(I64)],
     "dnet_layer_info": [P, INT, P, P],
+    "dnet_plan": [INT, P],
     "dnet_get_params": [P, P],
     "dnet_set_params": [P, P],
     "dnet_get_grads": [P, P],
@@ -446,6 +447,12 @@ class DensityNet:
         call("dnet_mse", self.handle, _ptr(y), _ptr(t), y.numel(), C.byref(loss), _ptr(dy) if dy is not None else None,
              _stream())
         return loss.value
+
+
+def dnet_plan(S: int) -> list[int]:
+    edges = (C.c_int * len(LAYER_NAMES))()
+    call("dnet_plan", S, C.cast(edges, P))
+    return list(edges)
 
 
 def crop(box, D: int, S: int, origin, sym: int, patch) -> None:

@@ -464,12 +464,19 @@ void make_layers(dnet* N) {
 
 unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
 
-// edge of the output of layer i for patch edge S
+// edge of the output of layer i for patch edge S: encoder levels S, S/2, S/4,
+// S/8 (the stride-2 layer opens its level), decoder levels S/4, S/2, S (the
+// upsampling conv opens its level), and the 1^3 output layer at S
 int out_edge(int i, int S) {
-    if (i <= C1B || i >= C7A) return S;
-    if (i <= C2B || (i >= C6A && i <= U1)) return S / 2;
-    if (i <= C3B || (i >= C5A && i <= U2)) return S / 4;
-    return S / 8;
+    static const int div[NLAYER] = {1, 1,          // c1a c1b
+                                    2, 2, 2,       // d1 c2a c2b
+                                    4, 4, 4,       // d2 c3a c3b
+                                    8, 8, 8,       // d3 c4a c4b
+                                    4, 4, 4,       // u3 c5a c5b
+                                    2, 2, 2,       // u2 c6a c6b
+                                    1, 1, 1,       // u1 c7a c7b
+                                    1};            // out
+    return S / div[i];
 }
 
 void ensure_buffers(dnet* N, int S) {
@@ -633,6 +640,13 @@ int dnet_layer_info(const dnet* N, int layer, int* info6, int64_t* offsets2) {
         info6[5] = l.stride;
         offsets2[0] = l.w_off;
         offsets2[1] = l.b_off;
+    });
+}
+
+int dnet_plan(int S, int* edges) {
+    return dguard([&] {
+        if (!edges || S < 8 || S % 8) fail(CHF_EINVAL, "dnet_plan: S must be a positive multiple of 8");
+        for (int i = 0; i < NLAYER; ++i) edges[i] = out_edge(i, S);
     });
 }
 

@@ -80,3 +80,17 @@ def test_projector_tables_match_oracle():
         assert np.array_equal(rank[off[a]:off[a + 1]], rows_o)
         dense = Bm[rows_o, 4 * a:4 * a + 4].toarray()
         assert np.allclose(beta[off[a]:off[a + 1]], dense, rtol=1e-14, atol=1e-17)
+
+
+def test_density_net_plan_matches_architecture():
+    # every layer's input edge must equal its producer's output edge
+    # (stride-2 layers halve, upsampling doubles); the oracle's forward pass
+    # gives the reference edges
+    import numpy as np
+    from oracle import unet as U
+    S = 16
+    edges = B.dnet_plan(S)
+    p = U.init_params(C=4, seed=0)
+    _, tape = U.forward(p, np.zeros((1, S, S, S)), keep=True)
+    ref = {name: z.shape[1] for name, _, z, _, _ in tape}
+    assert edges == [ref[name] for name in B.LAYER_NAMES]
