@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--dtype", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--nvec", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 4 GiB device copy (reference dispatch for HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="JSON with counter-derived HBM bytes per H X launch for this workload")
     return ap.parse_args()
@@ -39,7 +41,7 @@ def parse():
 
 def cpu_baseline(degree: int) -> dict:
     """The FP64 oracle filter timed on the host on a bounded sample: the
-    0.55 nm cluster's full grid (72,455 points) with 128 vectors, same degree."""
+    0.55 nm cluster's full grid (72,455 points) with 1024 vectors, same degree."""
     import numpy as np
     from oracle import chfsi as OC
     from oracle import grid as OG
@@ -50,7 +52,7 @@ def cpu_baseline(degree: int) -> dict:
     c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
     g = OG.build_grid(c.domain_radius(), wl.h)
     Ho = OH.build_hamiltonian(g, c.pos, c.species, OH.PseudoParams())
-    nvec = 128
+    nvec = 1024
     X = random_block(g.n, nvec, wl.x_seed)
     b, tmin, _ = OC.lanczos_bound(Ho.apply, random_block(g.n, 1, wl.lanczos_seed)[:, 0])
     a0 = float(Ho.veff.min())
@@ -167,6 +169,13 @@ def main():
                      "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"])},
         "wall_s": wall,
     }
+    if args.copy_calibration:
+        src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.degree)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,76 @@
+"""Train the initial-density network on converged densities and evaluate the
+SCF steps it saves.
+
+    python -m paper_2303_00790_amd.train_density --train 40 --steps 1500 --eval 3 --out results.json
+
+Training clusters: seeded random H-passivated Si spheres (diameters drawn
+uniformly from --train-diam, position noise 0.05 angstrom), each converged
+with the SCF to SRE < 1e-4 Ry.  Evaluation clusters use unseen seeds and
+--eval-diam; each runs the SCF from the superposition start and from the
+network's start, reporting steps to convergence and the energy difference.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def main(argv=None):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from paper_2303_00790_amd import binding as B
+    from paper_2303_00790_amd import density_model as DM
+    from synth.cluster import make_cluster
+    from synth.workloads import MODEL_PP
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--train", type=int, default=40)
+    ap.add_argument("--train-diam", type=float, nargs=2, default=(1.5, 2.5))
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--patch", type=int, default=48)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--eval", type=int, default=3)
+    ap.add_argument("--eval-diam", type=float, default=3.0)
+    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--params-out", default=None)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.perf_counter()
+    data = DM.make_dataset(args.train, 10000, tuple(args.train_diam), MODEL_PP, sigma=0.05, log=log)
+    t_data = time.perf_counter() - t0
+    net = B.DensityNet(args.channels, seed=1)
+    t1 = time.perf_counter()
+    losses = DM.train(net, data, args.steps, patch=args.patch, lr=args.lr, log=log)
+    t_train = time.perf_counter() - t1
+    evals = [make_cluster(5.0 * args.eval_diam, 20000 + i, sigma_angstrom=0.02) for i in range(args.eval)]
+    rows = DM.evaluate(net, evals, MODEL_PP, dtype=args.dtype, log=log)
+    res = {
+        "train_clusters": len(data), "train_diam_nm": list(args.train_diam), "steps": args.steps,
+        "patch": args.patch, "channels": args.channels, "data_s": t_data, "train_s": t_train,
+        "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
+        "eval_diam_nm": args.eval_diam, "eval": rows,
+        "mean_steps_sad": float(np.mean([r["steps_sad"] for r in rows])),
+        "mean_steps_net": float(np.mean([r["steps_net"] for r in rows])),
+        "max_de_per_atom": float(max(r["de_per_atom"] for r in rows)),
+    }
+    log(json.dumps(res))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+    if args.params_out:
+        np.save(args.params_out, net.get_params())
+
+
+if __name__ == "__main__":
+    main()
