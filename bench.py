@@ -31,6 +31,13 @@ def parse():
     ap.add_argument("--workload", default="d16nm")
     ap.add_argument("--dtype", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--nvec", type=int, default=None)
+    ap.add_argument("--ordering", default="hilbert", choices=["hilbert", "lex"],
+                    help="grid row order: blockwise Hilbert (tiled kernel) or lexicographic (neighbour-table kernel)")
+    ap.add_argument("--generic", action="store_true",
+                    help="use the neighbour-table kernel on the Hilbert order too (isolates the ordering effect)")
+    ap.add_argument("--cpu-sample", default="auto",
+                    help="oracle sample: 'auto' (0.55 nm grid x 1024 vectors) or 'workload:K' (this workload's "
+                         "grid x K vectors)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 4 GiB device copy (reference dispatch for HBM byte counters)")
@@ -39,20 +46,26 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(degree: int) -> dict:
-    """The FP64 oracle filter timed on the host on a bounded sample: the
-    0.55 nm cluster's full grid (72,455 points) with 1024 vectors, same degree."""
+def cpu_baseline(degree: int, sample: str = "auto", workload: str = "d16nm") -> dict:
+    """The FP64 oracle filter timed on the host on a bounded sample: by
+    default the 0.55 nm cluster's full grid (72,455 points) with 1024 vectors;
+    'workload:K' takes the benched workload's own grid with K vectors."""
     import numpy as np
     from oracle import chfsi as OC
     from oracle import grid as OG
     from oracle import hamiltonian as OH
     from synth.cluster import make_cluster, random_block
     from synth.workloads import WORKLOADS
-    wl = WORKLOADS["si35h36"]
+    if sample == "auto":
+        wl, nvec = WORKLOADS["si35h36"], 1024
+    else:
+        kind, _, k = sample.partition(":")
+        if kind != "workload" or not k.isdigit():
+            raise SystemExit(f"bench.py: bad --cpu-sample {sample!r}")
+        wl, nvec = WORKLOADS[workload], int(k)
     c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
     g = OG.build_grid(c.domain_radius(), wl.h)
     Ho = OH.build_hamiltonian(g, c.pos, c.species, OH.PseudoParams())
-    nvec = 1024
     X = random_block(g.n, nvec, wl.x_seed)
     b, tmin, _ = OC.lanczos_bound(Ho.apply, random_block(g.n, 1, wl.lanczos_seed)[:, 0])
     a0 = float(Ho.veff.min())
@@ -61,7 +74,7 @@ def cpu_baseline(degree: int) -> dict:
     OC.chebyshev_filter(Ho.apply, X, degree, a, b, a0)
     dt = time.perf_counter() - t0
     return {"value": g.n * nvec / dt, "unit": "gridpt*vectors/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle degree-{degree} filter, 0.55 nm Si35H36 grid ({g.n} points) x {nvec} vectors "
+            "sample": f"FP64 oracle degree-{degree} filter, {wl.name} grid ({g.n} points) x {nvec} vectors "
                       f"(scipy CSR SpMM, single-threaded), {dt:.1f} s"}
 
 
@@ -88,7 +101,10 @@ def main():
     t_setup = time.perf_counter()
     c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
     radius = c.domain_radius()
-    H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, B.ORDER_HILBERT, keep_nbr=False, dtypes=3)
+    lex = args.ordering == "lex"
+    H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, B.ORDER_LEX if lex else B.ORDER_HILBERT,
+                      keep_nbr=lex or args.generic, dtypes=3)
+    generic = lex or args.generic
     _, rows_np, _ = H.export_ordering()
     rows = torch.from_numpy(rows_np).cuda()
     inside = torch.zeros(H.n_rows, dtype=torch.bool, device="cuda")
@@ -112,7 +128,7 @@ def main():
           file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
-        H.filter(X, W, wl.degree, a, b, a0)
+        H.filter(X, W, wl.degree, a, b, a0, generic=generic)
     torch.cuda.synchronize()
     B.timer(True)
     stream = torch.cuda.current_stream()
@@ -121,7 +137,7 @@ def main():
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        H.filter(X, W, wl.degree, a, b, a0)
+        H.filter(X, W, wl.degree, a, b, a0, generic=generic)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -141,8 +157,9 @@ def main():
     alg_bytes_per_launch = per_pass_bytes / wl.degree
     hx_avg_s = tm["hx_ms"] / 1e3 / max(1, launches)
     achieved = alg_bytes_per_launch / hx_avg_s / 1e9
+    kernel = ("hx_generic_kernel" if generic else "hx_tiled_kernel")
     traffic = None
-    if os.path.exists(args.traffic):
+    if not generic and os.path.exists(args.traffic):
         rec = json.load(open(args.traffic)).get(f"{wl.name}:{dtype_name}:{nvec}")
         if rec:
             traffic = rec.get("bytes_per_launch")
@@ -159,14 +176,18 @@ def main():
         "vs_baseline": None,
         "dtype": dtype_name,
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.description}", "points": n_pts, "rows": H.n_rows,
+        "config": {"workload": f"{wl.name}: {wl.description}", "ordering": args.ordering, "kernel": kernel,
+                   "points": n_pts, "rows": H.n_rows,
                    "vectors": nvec, "degree": wl.degree, "projector_atoms": H.n_proj, "h_bohr": wl.h,
                    "per_degree_rate": value * wl.degree},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "hx_tiled_kernel", "avg_launch_ms": hx_avg_s * 1e3,
+                     "kernel": kernel, "avg_launch_ms": hx_avg_s * 1e3,
                      "alg_bytes_per_launch": alg_bytes_per_launch,
-                     "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"])},
+                     "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"]),
+                     "kb_gather_launches": tm["gather_launches"],
+                     "kb_reduce_avg_ms": tm["reduce_ms"] / max(1, tm["reduce_launches"]),
+                     "kb_reduce_launches": tm["reduce_launches"]},
         "wall_s": wall,
     }
     if args.copy_calibration:
@@ -177,7 +198,7 @@ def main():
         out["copy_calibration_bytes"] = 2 * src.numel() * 4
         del src, dst
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl.degree)
+        out["cpu_baseline"] = cpu_baseline(wl.degree, args.cpu_sample, wl.name)
     print(json.dumps(out), flush=True)
 
 

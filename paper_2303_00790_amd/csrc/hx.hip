@@ -393,6 +393,15 @@ __device__ inline V lz() {
     return v;
 }
 
+__device__ inline void load4(const float* p, float* o) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+}
+__device__ inline void load4(const double* p, double* o) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+    o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+}
+
 // raw buffer access (vector memory through a 128-bit resource descriptor)
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
@@ -407,15 +416,18 @@ __device__ inline void bstore(V v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
-// Workgroup of 1024 threads = 64 columns x 16 lanes; a lane holds 8 bytes
-// (2 floats or 1 double) of a 128-byte vector chunk (32 FP32 / 16 FP64
-// vectors); one workgroup per tile (one 8^3 block x one vector chunk), 16
-// waves.  The KB coefficients of the atoms touching the block can be staged
-// in LDS (STAGE, up to kMaxBlockAtoms) instead of read from global memory.
+// Workgroup of 64 columns x LANES lanes; a lane holds 8 bytes (2 floats or
+// 1 double) of an 8*LANES-byte vector chunk; one workgroup per tile (one 8^3
+// block x one vector chunk).  LANES = 16 (used) gives 128-byte row segments
+// and 1024 threads; LANES = 8 gives 64-byte segments and half the LDS, so two
+// workgroups share a CU, but measured 18 % slower on the 16 nm cluster (half
+// cache lines per request).  The KB coefficients of the atoms touching the
+// block can be staged in LDS (STAGE, up to kMaxBlockAtoms) instead of read
+// from global memory.
 constexpr int kMaxBlockAtoms = 64;
 
-template <class T, bool STAGE>
-__global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
+template <class T, bool STAGE, int LANES, bool EMIT>
+__global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
                                                         const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
                                                         const int32_t* __restrict__ ent_off,
                                                         const int32_t* __restrict__ ent_atom,
@@ -424,26 +436,37 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
                                                         const int32_t* __restrict__ blk_atom_off,
                                                         const int32_t* __restrict__ blk_atoms, const T* __restrict__ C,
                                                         int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
-                                                        int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
+                                                        int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k,
+                                                        const int64_t* __restrict__ pair_start,
+                                                        const uint16_t* __restrict__ gat_row,
+                                                        const T* __restrict__ gat_beta, T* __restrict__ part) {
     using V = typename Lane<T>::V;
     constexpr int LN = Lane<T>::N;       // elements per lane
-    constexpr int CH = 16 * LN;          // vectors per chunk
+    constexpr int CH = LANES * LN;       // vectors per chunk
+    static_assert(!EMIT || STAGE, "the coefficient epilogue needs the staged block atom list");
+    constexpr int NT = 64 * LANES;       // threads
+    constexpr int LSH = LANES == 16 ? 4 : 3;
+    constexpr int CPW = 64 / LANES;      // columns per wave
+    constexpr int G = 16 / LANES;        // sibling chunks sharing a 128-byte line
+    static_assert(LANES == 16 || LANES == 8, "LANES is 8 or 16");
     // LDS plane: the full 20 x 20 square x in [-6, 14), y in [-6, 14) (corners
     // unused) so every neighbour is a constant offset from the centre
-    __shared__ V plane[2][400][16];
-    __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][16][4];
+    __shared__ V plane[2][400][LANES];
+    __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][LANES][4];
 
     // XCD-aware tile order: workgroup ids are dealt round-robin to the 8
-    // XCDs; give each XCD a contiguous run of the (chunk-major, Hilbert-
-    // ordered) tile sequence so that neighbouring blocks share its L2.
-    const int64_t ntiles = n_blocks * n_chunks;
+    // XCDs; give each XCD a contiguous run of the tile sequence (chunk groups
+    // major, Hilbert-ordered blocks, the G sibling chunks of a block last) so
+    // that neighbouring blocks share its L2 and sibling chunks share lines.
+    const int n_groups = (n_chunks + G - 1) / G;
+    const int64_t ntiles = n_blocks * n_groups * G;
     const int64_t per_xcd = (ntiles + 7) / 8;
     const int64_t tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tile >= ntiles) return;
 
     const int t = threadIdx.x;
-    const int p = t & 15;                // lane within the chunk
-    const int col = t >> 4;              // column 0..63
+    const int p = t & (LANES - 1);       // lane within the chunk
+    const int col = t >> LSH;            // column 0..63
     const int cx = col & 7, cy = col >> 3;
     const int wave = t >> 6;
     const unsigned es = sizeof(T);
@@ -467,8 +490,13 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
         unsigned hoff[3];
     };
     TileIO io;
-    io.chunk = int(tile / n_blocks);
-    io.blk = tile - int64_t(io.chunk) * n_blocks;
+    {
+        const int64_t per_group = n_blocks * G;
+        const int grp = int(tile / per_group);
+        const int64_t rem = tile - grp * per_group;
+        io.blk = rem / G;
+        io.chunk = grp * G + int(rem - io.blk * G);
+    }
 #pragma unroll
     for (int f = 0; f < 6; ++f) io.nbs[f] = bnb[6 * io.blk + f];
     {
@@ -481,14 +509,14 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
     io.rZm = res_x(io.nbs[4]);
     io.rZp = res_x(io.nbs[5]);
     io.rZ = make_rsrc(Z ? Z + io.blk * kBlockPts * ldz : X, Z ? unsigned(kBlockPts) * unsigned(ldz) * es : 0u);
-    // Halo slot u of a wave covers 4 consecutive halo rows, all on one side
+    // Halo slot u of a wave covers CPW consecutive halo rows, all on one side
     // of the block (48 rows per side), so the side is wave-uniform.
     int hrow[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-        const int hr0 = 4 * wave + 64 * u;
+        const int hr0 = CPW * wave + 64 * u;
         const int side = __builtin_amdgcn_readfirstlane(hr0 / 48);
-        const int hr = (t >> 4) + 64 * u;
+        const int hr = col + 64 * u;
         const int rem = hr - 48 * side;
         int lx, ly, x, y, nb;
         if (side < 2) {
@@ -523,7 +551,9 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
 #pragma unroll
         for (int u = 0; u < 3; ++u) plane[b][hrow[u]][p] = hv[u];
     };
-    auto load_z = [&](const TileIO& io, int z) -> V { return bload<V>(io.rZ, io.off_z + unsigned(z) * plane_z); };
+    auto load_z = [&](const TileIO& io, int z) -> V {
+        return bload<V>(io.rZ, io.off_z + unsigned(z) * plane_z);
+    };
 
     V w[20];
 #pragma unroll
@@ -545,8 +575,8 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
             na = min(blk_atom_off[io.blk + 1] - a0, kMaxBlockAtoms);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int e = t + 1024 * u;       // (atom slot, lm, lane)
-                const int sl = e >> 6, lm = (e >> 4) & 3, lp = e & 15;
+                const int e = t + NT * u;         // (atom slot, lm, lane)
+                const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
                 const int vb = io.chunk * CH + lp * LN;
                 if (sl < na && vb < nvec)
                     cstage[u] = *reinterpret_cast<const V*>(C + (int64_t(blk_atoms[a0 + sl]) * 4 + lm) * nvec + vb);
@@ -599,8 +629,8 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
         if (STAGE && ent_off) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int e = t + 1024 * u;
-                const int sl = e >> 6, lm = (e >> 4) & 3, lp = e & 15;
+                const int e = t + NT * u;
+                const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
                 if (sl < kMaxBlockAtoms) cst[sl][lp][lm] = cstage[u];
             }
         }
@@ -658,31 +688,161 @@ __global__ void __launch_bounds__(1024) hx_tiled_kernel(int64_t n_blocks, int n_
                 bstore<V>(in ? r[z] : lz<V>(), rY, off_y + unsigned(z) * plane_y);
             }
         }
+
+        // Epilogue (EMIT): KB coefficient partials of the output,
+        //   part[q][lm][v] = sum over the support rows of atom a(q) inside
+        //   this block of (h^3 beta_alm(row)) Y(row, v),
+        // one per (block, atom) pair q.  The block's gather entries (pairs in
+        // slot order, rows ascending within a pair) are cut into 64 equal
+        // intervals, one per column group; pairs that straddle an interval
+        // boundary are summed in a second phase, in interval order, so the
+        // result does not depend on scheduling.
+        if (EMIT) {
+            const int q0 = blk_atom_off[cur_blk];
+            const int na = blk_atom_off[cur_blk + 1] - q0;
+            if (na > 0) {
+                V* ylds = &plane[0][0][0];                  // [512][LANES]
+                V* tails = ylds + kBlockPts * LANES;        // [64][4][LANES]
+                int* po = reinterpret_cast<int*>(tails + 256 * LANES);   // [na + 1] local pair starts
+#pragma unroll
+                for (int z = 0; z < 8; ++z) {
+                    const bool in = (bmask[8 * cur_blk + z] >> (cx + 8 * cy)) & 1;
+                    ylds[(col + 64 * z) * LANES + p] = in ? r[z] : lz<V>();
+                }
+                const int64_t e_base = pair_start[q0];
+                for (int i = t; i <= na; i += NT) po[i] = int(pair_start[q0 + i] - e_base);
+                __syncthreads();
+                const int E = po[na];
+                const int L = (E + 63) >> 6;
+                const int j0 = min(col * L, E), j1 = min(j0 + L, E);
+                V hd[4];
+                int s_head = -1;
+                if (j0 < j1) {
+                    int sl = 0;
+                    while (po[sl + 1] <= j0) ++sl;
+                    for (;;) {
+                        const int jb = max(po[sl], j0), je = min(po[sl + 1], j1);
+                        V acc[4];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) acc[m] = lz<V>();
+                        // the group's LANES lanes load LANES entries at once
+                        // (one memory round trip), then broadcast them in turn
+                        // within the group (a 16-lane row of the wave)
+                        const uint16_t* gr = gat_row + e_base;
+                        const T* gb = gat_beta + 4 * e_base;
+                        for (int jc = jb; jc < je; jc += LANES) {
+                            const int jj = jc + p;
+                            int u_own = 0;
+                            T b_own[4] = {T(0), T(0), T(0), T(0)};
+                            if (jj < je) {
+                                u_own = gr[jj];
+                                load4(gb + 4 * int64_t(jj), b_own);
+                            }
+                            const int cnt = min(LANES, je - jc);
+                            for (int kk = 0; kk < cnt; ++kk) {
+                                const int u = __shfl(u_own, kk, LANES);
+                                const V y = ylds[u * LANES + p];
+#pragma unroll
+                                for (int m = 0; m < 4; ++m) acc[m] = lfma(__shfl(b_own[m], kk, LANES), y, acc[m]);
+                            }
+                        }
+                        const bool before = po[sl] < j0, after = po[sl + 1] > j1;
+                        if (after) {
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) tails[(col * 4 + m) * LANES + p] = acc[m];
+                        } else if (before) {
+                            s_head = sl;
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) hd[m] = acc[m];
+                        } else if (cur_vok) {
+#pragma unroll
+                            for (int m = 0; m < 4; ++m)
+                                *reinterpret_cast<V*>(part + (int64_t(q0 + sl) * 4 + m) * nvec + vbase) = acc[m];
+                        }
+                        if (je == j1) break;
+                        ++sl;
+                    }
+                }
+                __syncthreads();
+                if (s_head >= 0 && cur_vok) {
+                    const int g_first = po[s_head] / L;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        V tot = tails[(g_first * 4 + m) * LANES + p];
+                        for (int g = g_first + 1; g < col; ++g) tot = ladd(tot, tails[(g * 4 + m) * LANES + p]);
+                        tot = ladd(tot, hd[m]);
+                        *reinterpret_cast<V*>(part + (int64_t(q0 + s_head) * 4 + m) * nvec + vbase) = tot;
+                    }
+                }
+            }
+        }
     }
 }
 
+// C[a][lm][v] = sum of the partials of atom a's (block, atom) pairs, blocks
+// ascending.  One workgroup per atom; 16-byte quads over the 4 * nvec values.
 template <class T>
-void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
-                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only) {
-    constexpr int CH = 16 * Lane<T>::N;
+__global__ void __launch_bounds__(256) kb_reduce_kernel(const int32_t* __restrict__ apair_off,
+                                                        const int32_t* __restrict__ apair_q, const T* __restrict__ part,
+                                                        int nvec, T* __restrict__ C) {
+    using V = typename Quad<T>::V;
+    constexpr int QN = Quad<T>::N;
+    const int a = blockIdx.x;
+    const int64_t n = 4 * int64_t(nvec);
+    const int k0 = apair_off[a], k1 = apair_off[a + 1];
+    for (int64_t e = int64_t(threadIdx.x) * QN; e < n; e += 256 * QN) {
+        V acc = vzero<V>();
+        for (int k = k0; k < k1; ++k) acc = vadd(acc, *reinterpret_cast<const V*>(part + int64_t(apair_q[k]) * n + e));
+        *reinterpret_cast<V*>(C + int64_t(a) * n + e) = acc;
+    }
+}
+
+constexpr int kLanes = 16;
+
+template <class T>
+static const T* gat_beta_of(const chf_ham* H) {
+    return std::is_same<T, double>::value ? H->gat_beta64.as<T>() : H->gat_beta32.as<T>();
+}
+
+template <class T, int LANES>
+static void launch_hx_tiled_l(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz,
+                              int nvec, const T* C, double alpha, double shift, double beta, hipStream_t s,
+                              bool lap_only, T* part) {
+    constexpr int CH = LANES * Lane<T>::N;
+    constexpr int G = 16 / LANES;
     const int n_chunks = (nvec + CH - 1) / CH;
-    const int64_t nt = H->grid.n_blocks * n_chunks;
-    const int64_t nwg = ((nt + 7) / 8) * 8;
+    const int64_t nt = H->grid.n_blocks * int64_t((n_chunks + G - 1) / G) * G;
+    const dim3 grid(unsigned(((nt + 7) / 8) * 8)), block(64 * LANES);
     const bool kb = !lap_only && H->proj.n_proj > 0;
     const bool stage = kb && H->proj.max_block_atoms <= kMaxBlockAtoms;
     const int32_t* eo = kb ? H->ent_off32.as<int32_t>() : nullptr;
     const StepCoef<T> coef = make_coef<T>(H, alpha, shift, beta);
     const T* veff = lap_only ? nullptr : veff_of<T>(H);
-    if (stage)
-        hx_tiled_kernel<T, true><<<dim3(unsigned(nwg)), dim3(1024), 0, s>>>(
-            H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,
-            H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),
-            H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef);
+#define CHF_TILED_ARGS                                                                                              \
+    H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,                \
+        H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),     \
+        H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef, H->pair_start.as<int64_t>(),             \
+        H->gat_row.as<uint16_t>(), gat_beta_of<T>(H), part
+    if (stage && part)
+        hx_tiled_kernel<T, true, LANES, true><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
+    else if (stage)
+        hx_tiled_kernel<T, true, LANES, false><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
     else
-        hx_tiled_kernel<T, false><<<dim3(unsigned(nwg)), dim3(1024), 0, s>>>(
-            H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,
-            H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),
-            H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef);
+        hx_tiled_kernel<T, false, LANES, false><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
+#undef CHF_TILED_ARGS
+    LAUNCH_CHECK();
+}
+
+template <class T>
+void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
+                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only, T* part) {
+    launch_hx_tiled_l<T, kLanes>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only, part);
+}
+
+template <class T>
+static void launch_kb_reduce(chf_ham* H, const T* part, int nvec, T* C, hipStream_t s) {
+    kb_reduce_kernel<T><<<dim3(unsigned(H->proj.n_proj)), dim3(256), 0, s>>>(
+        H->apair_off.as<int32_t>(), H->apair_q.as<int32_t>(), part, nvec, C);
     LAUNCH_CHECK();
 }
 
@@ -692,7 +852,7 @@ void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, con
 // ---------------------------------------------------------------------------
 struct KernelTimer {
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[2];   // 0: H X, 1: KB gather
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[3];   // 0: H X, 1: KB gather, 2: KB partial sums
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -744,15 +904,42 @@ bool tiled_ok(const chf_ham* H, const void* X, int64_t ldx, const void* Y, int64
     return true;
 }
 
+// Largest partial-coefficient buffer the fused epilogue may use; beyond it
+// the coefficients come from the standalone gather.
+constexpr size_t kMaxPartBytes = size_t(32) << 30;
+
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only) {
-    H->kb_coef.ensure(size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * sizeof(T));
-    T* C = H->kb_coef.as<T>();
-    if (H->proj.n_proj > 0 && !lap_only) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, C, s); });
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only, int kb_flags) {
+    const bool kb = H->proj.n_proj > 0 && !lap_only;
+    const size_t cbytes = size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * sizeof(T);
+    H->kb_coef.ensure(cbytes);
+    const bool reuse = kb && (kb_flags & KB_REUSE) && H->kb_ready == static_cast<const void*>(X) &&
+                       H->kb_ready_ld == ldx && H->kb_ready_nvec == nvec && H->kb_ready_es == int(sizeof(T));
+    H->kb_ready = nullptr;
+    if (kb && !reuse) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, H->kb_coef.as<T>(), s); });
+    const T* C = H->kb_coef.as<T>();
     const bool tiled = force_kernel != 1 && tiled_ok<T>(H, X, ldx, Y, ldy, Z, ldz, nvec);
     if (tiled) {
-        timed(0, s, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
+        const size_t pbytes = size_t(H->n_block_pairs) * 4 * size_t(nvec) * sizeof(T);
+        const bool emit = kb && (kb_flags & KB_EMIT) && H->proj.max_block_atoms <= kMaxBlockAtoms &&
+                          gat_beta_of<T>(H) != nullptr && H->n_block_pairs > 0 && pbytes <= kMaxPartBytes;
+        T* part = nullptr;
+        if (emit) {
+            H->kb_part.ensure(pbytes);
+            H->kb_next.ensure(cbytes);
+            part = H->kb_part.as<T>();
+        }
+        timed(0, s, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only, part); });
+        if (emit) {
+            timed(2, s, [&] { launch_kb_reduce<T>(H, part, nvec, H->kb_next.as<T>(), s); });
+            std::swap(H->kb_coef.p, H->kb_next.p);
+            std::swap(H->kb_coef.bytes, H->kb_next.bytes);
+            H->kb_ready = Y;
+            H->kb_ready_ld = ldy;
+            H->kb_ready_nvec = nvec;
+            H->kb_ready_es = int(sizeof(T));
+        }
     } else {
         if (!H->has_nbr) fail(CHF_EUNSUPPORTED, "generic H X needs the neighbour table (keep_nbr) for this layout");
         timed(0, s, [&] { launch_hx_generic<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
@@ -766,7 +953,7 @@ void timer_enable(int on) {
 
 void timer_read(double* ms, int64_t* launches) {
     HIP_CHECK(hipDeviceSynchronize());
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 3; ++w) {
         double t = 0;
         for (auto& p : g_timer.spans[w]) {
             float f = 0;
@@ -779,9 +966,9 @@ void timer_read(double* ms, int64_t* launches) {
 }
 
 template void hx_step<float>(chf_ham*, const float*, int64_t, float*, int64_t, const float*, int64_t, int, double,
-                             double, double, hipStream_t, int, bool);
+                             double, double, hipStream_t, int, bool, int);
 template void hx_step<double>(chf_ham*, const double*, int64_t, double*, int64_t, const double*, int64_t, int,
-                              double, double, double, hipStream_t, int, bool);
+                              double, double, double, hipStream_t, int, bool, int);
 template void launch_kb_gather<float>(chf_ham*, const float*, int64_t, int, float*, hipStream_t);
 template void launch_kb_gather<double>(chf_ham*, const double*, int64_t, int, double*, hipStream_t);
 

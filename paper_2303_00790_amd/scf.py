@@ -36,15 +36,20 @@ def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nve
     code = B.CHF_F64 if dtype == "f64" else B.CHF_F32
     _, rows_np, _ = H.export_ordering()
     rows = torch.from_numpy(rows_np).cuda()
-    gen = torch.Generator(device="cpu")
+    # start block: i.i.d. N(0, 1) drawn in FP64 on the device (seeded; the
+    # same numbers for either work dtype), written to the inside rows in
+    # row chunks so no FP64 copy of the whole block is needed
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(x_seed)
     X = torch.zeros((H.n_rows, M), dtype=tdt, device="cuda")
-    x0 = np.random.default_rng(x_seed).standard_normal((H.n_points, M))
-    X[rows] = torch.from_numpy(x0).to(device="cuda", dtype=tdt)
+    step = max(1, (1 << 27) // M)
+    for r0 in range(0, H.n_points, step):
+        r = rows[r0:r0 + step]
+        X[r] = torch.randn((r.numel(), M), generator=gen, dtype=torch.float64, device="cuda").to(tdt)
     v0 = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
     v0[rows] = torch.from_numpy(np.random.default_rng(lanczos_seed).standard_normal(H.n_points)).cuda()
     eii = B.ion_energy(cluster.pos, cluster.species, pp)
     prm = B.ScfParams(ne, M, degree, 4, 1, 10, code, code, 6, 0.3, 1e-12, eii)
-    del gen
     return dict(H=H, ctx=ctx, prm=prm, X=X, W=torch.zeros_like(X), v0=v0, rows=rows, ne=ne, M=M)
 
 

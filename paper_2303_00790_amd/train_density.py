@@ -39,37 +39,44 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=3)
     ap.add_argument("--eval-diam", type=float, default=3.0)
     ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--eval-seed", type=int, default=20000)
     ap.add_argument("--out", default=None)
     ap.add_argument("--params-out", default=None)
+    ap.add_argument("--params-in", default=None, help="skip data and training; evaluate these weights")
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
-    t0 = time.perf_counter()
-    data = DM.make_dataset(args.train, 10000, tuple(args.train_diam), MODEL_PP, sigma=0.05, log=log)
-    t_data = time.perf_counter() - t0
     net = B.DensityNet(args.channels, seed=1)
-    t1 = time.perf_counter()
-    losses = DM.train(net, data, args.steps, patch=args.patch, lr=args.lr, log=log)
-    t_train = time.perf_counter() - t1
-    evals = [make_cluster(5.0 * args.eval_diam, 20000 + i, sigma_angstrom=0.02) for i in range(args.eval)]
-    rows = DM.evaluate(net, evals, MODEL_PP, dtype=args.dtype, log=log)
-    res = {
-        "train_clusters": len(data), "train_diam_nm": list(args.train_diam), "steps": args.steps,
-        "patch": args.patch, "channels": args.channels, "data_s": t_data, "train_s": t_train,
-        "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
-        "eval_diam_nm": args.eval_diam, "eval": rows,
-        "mean_steps_sad": float(np.mean([r["steps_sad"] for r in rows])),
-        "mean_steps_net": float(np.mean([r["steps_net"] for r in rows])),
-        "max_de_per_atom": float(max(r["de_per_atom"] for r in rows)),
-    }
+    res = {"channels": args.channels}
+    if args.params_in:
+        net.set_params(np.load(args.params_in).astype(np.float32))
+        res["params_in"] = os.path.basename(args.params_in)
+    else:
+        t0 = time.perf_counter()
+        data = DM.make_dataset(args.train, 10000, tuple(args.train_diam), MODEL_PP, sigma=0.05, log=log)
+        t_data = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        losses = DM.train(net, data, args.steps, patch=args.patch, lr=args.lr, log=log)
+        t_train = time.perf_counter() - t1
+        res.update({"train_clusters": len(data), "train_diam_nm": list(args.train_diam), "steps": args.steps,
+                    "patch": args.patch, "data_s": t_data, "train_s": t_train,
+                    "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:]))})
+        if args.params_out:
+            np.save(args.params_out, net.get_params())
+        del data
+    if args.eval > 0:
+        evals = [make_cluster(5.0 * args.eval_diam, args.eval_seed + i, sigma_angstrom=0.02) for i in range(args.eval)]
+        rows = DM.evaluate(net, evals, MODEL_PP, dtype=args.dtype, log=log)
+        res.update({"eval_diam_nm": args.eval_diam, "eval_seeds": [args.eval_seed + i for i in range(args.eval)],
+                    "eval": rows, "mean_steps_sad": float(np.mean([r["steps_sad"] for r in rows])),
+                    "mean_steps_net": float(np.mean([r["steps_net"] for r in rows])),
+                    "max_de_per_atom": float(max(r["de_per_atom"] for r in rows))})
     log(json.dumps(res))
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)
-    if args.params_out:
-        np.save(args.params_out, net.get_params())
 
 
 if __name__ == "__main__":
