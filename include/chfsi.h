@@ -179,12 +179,10 @@ int chf_filter_generic(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, 
                        double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
 
 /* Kernel timing (instrumentation): while enabled, HIP events are recorded on
- * the launch stream around every H X launch (slot 0), every standalone
- * KB-gather launch (slot 1) and every sum of the per-block KB coefficient
- * partials that the filter's H X launches emit (slot 2).  chf_timer(1)
- * clears and enables, chf_timer(0) disables; chf_timer_read synchronises the
- * device and returns per slot the summed milliseconds (ms_host[3]) and the
- * launch counts (launches_host[3]). */
+ * the launch stream around every H X launch (slot 0) and every KB-gather
+ * launch (slot 1).  chf_timer(1) clears and enables, chf_timer(0) disables;
+ * chf_timer_read synchronises the device and returns per slot the summed
+ * milliseconds (ms_host[2]) and the launch counts (launches_host[2]). */
 int chf_timer(int enable);
 int chf_timer_read(double* ms_host, int64_t* launches_host);
 

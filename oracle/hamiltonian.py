@@ -12,14 +12,15 @@ Readings where the paper is silent:
   and z (13 points per axis, 37-point star), coefficients from Fornberg's
   closed form; psi = 0 at every grid point outside the sphere;
 * V_loc(r) = -sum_a Z_a erf(|r - R_a| / r_loc) / |r - R_a| with Z_Si = 4,
-  Z_H = 1, r_loc = 0.9 bohr for Si and 0.5 bohr for H, and the r -> 0 limit
-  -2 Z / (sqrt(pi) r_loc) (with the softer 0.9 bohr H width the Si-H bonds
-  are so weak that no HOMO-LUMO gap forms in the smallest cluster);
+  Z_H = 1, r_loc = 0.7 bohr for Si and 0.5 bohr for H, and the r -> 0 limit
+  -2 Z / (sqrt(pi) r_loc) (with a 0.9 bohr H width the Si-H bonds are so weak
+  that no HOMO-LUMO gap forms in the smallest cluster; with a 0.9 bohr Si
+  width the gap closes by 3 nm);
 * one s and one p Gaussian projector per Si in the Goedecker-Teter-Hutter
   form p_l(r) = N_l r^l exp(-r^2 / (2 r_c^2)), r_c = 1.2 bohr, normalised by
   int p_l^2 r^2 dr = 1, times real harmonics, cut at |r - R_a| <= 4.8 bohr;
-  KB energies h_s = 2.0 Ha, h_p = 0.0 Ha by default (chosen so that the
-  smallest cluster converges with a gap); H atoms carry no projector;
+  KB energies h_s = 3.0 Ha, h_p = 0.0 Ha by default (chosen so that clusters
+  from 0.55 to 4 nm converge with an open gap); H atoms carry no projector;
 * <beta|X> is the quadrature h^3 sum_q beta(q) X(q).
 """
 from __future__ import annotations
@@ -39,11 +40,11 @@ from .grid import Grid, HALF_ORDER, neighbour_table, offsets
 class PseudoParams:
     z_si: float = 4.0
     z_h: float = 1.0
-    r_loc: float = 0.9
+    r_loc: float = 0.7
     r_loc_h: float = 0.5
     r_c: float = 1.2
     r_cut: float = 4.8
-    h_s: float = 2.0
+    h_s: float = 3.0
     h_p: float = 0.0
 
     def charges(self, species: np.ndarray) -> np.ndarray:

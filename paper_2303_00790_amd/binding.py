@@ -216,11 +216,10 @@ def timer(enable: bool) -> None:
 
 
 def timer_read() -> dict:
-    ms = (C.c_double * 3)()
-    n = (C.c_int64 * 3)()
+    ms = (C.c_double * 2)()
+    n = (C.c_int64 * 2)()
     call("chf_timer_read", C.cast(ms, P), C.cast(n, P))
-    return {"hx_ms": ms[0], "hx_launches": n[0], "gather_ms": ms[1], "gather_launches": n[1],
-            "reduce_ms": ms[2], "reduce_launches": n[2]}
+    return {"hx_ms": ms[0], "hx_launches": n[0], "gather_ms": ms[1], "gather_launches": n[1]}
 
 
 class Context:

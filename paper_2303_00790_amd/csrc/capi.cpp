@@ -103,17 +103,14 @@ static void run_filter(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nve
     const double e = (b - a) / 2, c = (b + a) / 2;
     const double sigma1 = e / (a0 - c);
     double sigma = sigma1;
-    // every step but the last emits the KB coefficients of its output, which
-    // the next step (whose input that output is) reuses
-    hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, nvec, sigma1 / e, c, 0.0, s, force_kernel, false, m > 1 ? KB_EMIT : 0);
+    hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, nvec, sigma1 / e, c, 0.0, s, force_kernel);
     for (int k = 2; k <= m; ++k) {
         const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
         const double alpha = 2.0 * sigma_next / e, beta = sigma * sigma_next;
-        const int fl = KB_REUSE | (k < m ? KB_EMIT : 0);
         if (k % 2 == 0)
-            hx_step<T>(H, W, ldw, X, ldx, X, ldx, nvec, alpha, c, beta, s, force_kernel, false, fl);
+            hx_step<T>(H, W, ldw, X, ldx, X, ldx, nvec, alpha, c, beta, s, force_kernel);
         else
-            hx_step<T>(H, X, ldx, W, ldw, W, ldw, nvec, alpha, c, beta, s, force_kernel, false, fl);
+            hx_step<T>(H, X, ldx, W, ldw, W, ldw, nvec, alpha, c, beta, s, force_kernel);
         sigma = sigma_next;
     }
     if (m % 2 == 1)
@@ -218,12 +215,6 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
             std::vector<int32_t> off32(H->proj.blk_atom_off.begin(), H->proj.blk_atom_off.end());
             upload(H->blk_atom_off, off32, s);
             upload(H->blk_atoms, H->proj.blk_atoms, s);
-            build_block_gather(g, H->proj);
-            upload(H->pair_start, H->proj.pair_start, s);
-            upload(H->gat_row, H->proj.gat_row, s);
-            upload(H->apair_off, H->proj.apair_off, s);
-            upload(H->apair_q, H->proj.apair_q, s);
-            H->n_block_pairs = H->proj.blk_atom_off.back();
         }
         const double h3 = gd->h * gd->h * gd->h;
         const double gsc[4] = {h3, h3, h3, h3};
@@ -231,12 +222,10 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
         if (gd->dtypes & 2) {
             upload(H->sup_beta64, cast_scaled<double>(P.sup_beta, gsc), s);
             upload(H->ent_beta64, cast_scaled<double>(P.ent_beta, ssc), s);
-            if (!P.gat_beta.empty()) upload(H->gat_beta64, cast_scaled<double>(P.gat_beta, gsc), s);
         }
         if (gd->dtypes & 1) {
             upload(H->sup_beta32, cast_scaled<float>(P.sup_beta, gsc), s);
             upload(H->ent_beta32, cast_scaled<float>(P.ent_beta, ssc), s);
-            if (!P.gat_beta.empty()) upload(H->gat_beta32, cast_scaled<float>(P.gat_beta, gsc), s);
         }
         // local potential (FP64, all atoms)
         H->vloc.alloc(size_t(g.n_rows) * 8);

@@ -306,47 +306,4 @@ void build_block_atoms(const HostGrid& g, HostProj& P) {
     }
 }
 
-void build_block_gather(const HostGrid& g, HostProj& P) {
-    const int64_t nq = P.blk_atom_off.back();
-    P.pair_start.assign(size_t(nq) + 1, 0);
-    // a pair's entry count: the atom's support rows inside the block
-    auto range_of = [&](int64_t b, int32_t a, int64_t& j0, int64_t& j1) {
-        const int32_t* r0 = P.sup_row.data() + P.sup_off[size_t(a)];
-        const int32_t* r1 = P.sup_row.data() + P.sup_off[size_t(a) + 1];
-        const int32_t* lo = std::lower_bound(r0, r1, int32_t(b * kBlockPts));
-        const int32_t* hi = std::lower_bound(lo, r1, int32_t((b + 1) * kBlockPts));
-        j0 = lo - P.sup_row.data();
-        j1 = hi - P.sup_row.data();
-    };
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t b = 0; b < g.n_blocks; ++b)
-        for (int64_t q = P.blk_atom_off[size_t(b)]; q < P.blk_atom_off[size_t(b) + 1]; ++q) {
-            int64_t j0, j1;
-            range_of(b, P.blk_atoms[size_t(q)], j0, j1);
-            P.pair_start[size_t(q) + 1] = j1 - j0;
-        }
-    for (int64_t q = 0; q < nq; ++q) P.pair_start[size_t(q) + 1] += P.pair_start[size_t(q)];
-    const int64_t ne = P.pair_start.back();
-    P.gat_row.assign(size_t(ne), 0);
-    P.gat_beta.assign(size_t(ne) * 4, 0.0);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t b = 0; b < g.n_blocks; ++b)
-        for (int64_t q = P.blk_atom_off[size_t(b)]; q < P.blk_atom_off[size_t(b) + 1]; ++q) {
-            int64_t j0, j1;
-            range_of(b, P.blk_atoms[size_t(q)], j0, j1);
-            int64_t d = P.pair_start[size_t(q)];
-            for (int64_t j = j0; j < j1; ++j, ++d) {
-                P.gat_row[size_t(d)] = uint16_t(P.sup_row[size_t(j)] - b * kBlockPts);
-                for (int m = 0; m < 4; ++m) P.gat_beta[size_t(4 * d + m)] = P.sup_beta[size_t(4 * j + m)];
-            }
-        }
-    // per atom: its pairs in block order
-    P.apair_off.assign(size_t(P.n_proj) + 1, 0);
-    for (int64_t q = 0; q < nq; ++q) P.apair_off[size_t(P.blk_atoms[size_t(q)]) + 1]++;
-    for (int64_t a = 0; a < P.n_proj; ++a) P.apair_off[size_t(a) + 1] += P.apair_off[size_t(a)];
-    P.apair_q.assign(size_t(nq), 0);
-    std::vector<int32_t> fill(P.apair_off.begin(), P.apair_off.end() - 1);
-    for (int64_t q = 0; q < nq; ++q) P.apair_q[size_t(fill[size_t(P.blk_atoms[size_t(q)])]++)] = int32_t(q);
-}
-
 }  // namespace chf

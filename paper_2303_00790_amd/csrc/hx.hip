@@ -16,6 +16,7 @@
 //                     chunk), z-march with a 13-deep register window per
 //                     column, x/y halos staged in LDS (double-buffered).
 #include <cmath>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "kernels.hpp"
@@ -393,6 +394,30 @@ __device__ inline V lz() {
     return v;
 }
 
+// compile-time loop: f(integral_constant<int, K>) for K = B .. E-1
+template <int B, int E, class F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// value of lane K of this lane's 16-lane row (DPP row_newbcast)
+template <int K>
+__device__ inline int row_bcast(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x150 + K, 0xF, 0xF, false);
+}
+template <int K>
+__device__ inline float row_bcast(float v) {
+    return __builtin_bit_cast(float, row_bcast<K>(__builtin_bit_cast(int, v)));
+}
+template <int K>
+__device__ inline double row_bcast(double v) {
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(row_bcast<K>(w.x), row_bcast<K>(w.y)));
+}
+
 __device__ inline void load4(const float* p, float* o) {
     const float4 v = *reinterpret_cast<const float4*>(p);
     o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
@@ -426,7 +451,7 @@ __device__ inline void bstore(V v, __amdgpu_buffer_rsrc_t r, unsigned off) {
 // from global memory.
 constexpr int kMaxBlockAtoms = 64;
 
-template <class T, bool STAGE, int LANES, bool EMIT>
+template <class T, bool STAGE, int LANES>
 __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
                                                         const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
                                                         const int32_t* __restrict__ ent_off,
@@ -436,14 +461,10 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                                                         const int32_t* __restrict__ blk_atom_off,
                                                         const int32_t* __restrict__ blk_atoms, const T* __restrict__ C,
                                                         int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
-                                                        int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k,
-                                                        const int64_t* __restrict__ pair_start,
-                                                        const uint16_t* __restrict__ gat_row,
-                                                        const T* __restrict__ gat_beta, T* __restrict__ part) {
+                                                        int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
     using V = typename Lane<T>::V;
     constexpr int LN = Lane<T>::N;       // elements per lane
     constexpr int CH = LANES * LN;       // vectors per chunk
-    static_assert(!EMIT || STAGE, "the coefficient epilogue needs the staged block atom list");
     constexpr int NT = 64 * LANES;       // threads
     constexpr int LSH = LANES == 16 ? 4 : 3;
     constexpr int CPW = 64 / LANES;      // columns per wave
@@ -555,24 +576,27 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
         return bload<V>(io.rZ, io.off_z + unsigned(z) * plane_z);
     };
 
-    V w[20];
-#pragma unroll
-    for (int i = 0; i < 14; ++i) w[i] = load_plane(io, i - 6);
-    V hv0[3], hv[3];
-    load_halo(io, 0, hv0);
-    load_halo(io, 1, hv);
-    V zcur = load_z(io, 0);
-
     {
         const int vbase = io.chunk * CH + p * LN;
         const int64_t base = io.blk * kBlockPts;
-        // KB coefficients of this block's atoms: issue the loads now, park
-        // them in LDS after the march
+        const int64_t cur_blk = io.blk;
+        const bool cur_vok = io.vok;
+        const int lrow = cx + 8 * cy;             // this column's row in plane 0
+        // STAGE: the KB term is applied inside the march, row z at plane z.
+        // The entries of row z (atom slot, h_l beta_lm) are loaded by the
+        // column's 16 lanes together (lane i holds entry i) PD planes ahead,
+        // their row offsets PD + 1 planes ahead, and broadcast across the
+        // 16-lane group (one DPP row) when used.  The block atoms'
+        // coefficients are staged in LDS before the march.
+        constexpr bool INMARCH = STAGE && LANES == 16;
+        constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+        constexpr bool KEEP_R = !INMARCH;
+        const bool kb = ent_off != nullptr;
         int na = 0, a0 = 0;
         V cstage[4];
-        if (STAGE && ent_off) {
-            a0 = blk_atom_off[io.blk];
-            na = min(blk_atom_off[io.blk + 1] - a0, kMaxBlockAtoms);
+        if (STAGE && kb) {
+            a0 = blk_atom_off[cur_blk];
+            na = min(blk_atom_off[cur_blk + 1] - a0, kMaxBlockAtoms);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = t + NT * u;         // (atom slot, lm, lane)
@@ -584,10 +608,54 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                     cstage[u] = lz<V>();
             }
         }
+        // the X window of this column, the first two halo planes and Y_{k-1}
+        // of plane 0 (issued after the coefficient loads, whose chain of
+        // dependent loads is the longest)
+        V w[20];
+#pragma unroll
+        for (int i = 0; i < 14; ++i) w[i] = load_plane(io, i - 6);
+        V hv0[3], hv[3];
+        load_halo(io, 0, hv0);
+        load_halo(io, 1, hv);
+        V zcur = load_z(io, 0);
+        int e_lo[8], e_hi[8], e_slot[8];
+        T e_b[8][4];
+        auto load_offsets = [&](int z) {
+            e_lo[z] = ent_off[base + lrow + 64 * z];
+            e_hi[z] = ent_off[base + lrow + 64 * z + 1];
+        };
+        auto load_entries = [&](int z) {
+            const int en = e_lo[z] + p;
+            e_slot[z] = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) e_b[z][m] = T(0);
+            if (en < e_hi[z] && p < 16) {
+                e_slot[z] = ent_slot[en];
+                load4(ent_beta + 4 * int64_t(en), e_b[z]);
+            }
+        };
+        if (INMARCH && kb) {
+#pragma unroll
+            for (int z = 0; z <= PD; ++z) load_offsets(z);
+        }
         store_halo(0, hv0);
         plane[0][ctr][p] = w[6];
+        if (STAGE && kb) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = t + NT * u;
+                const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
+                if (sl < kMaxBlockAtoms) cst[sl][lp][lm] = cstage[u];
+            }
+        }
         __syncthreads();
+        if (INMARCH && kb) {
+#pragma unroll
+            for (int z = 0; z < PD; ++z) load_entries(z);
+        }
 
+        const __amdgpu_buffer_rsrc_t rY = make_rsrc(Y + base * ldy, unsigned(kBlockPts) * unsigned(ldy) * es);
+        const unsigned off_y = cur_vok ? (unsigned(lrow) * unsigned(ldy) + unsigned(vbase)) * es : kOOB;
         V r[8];
         const T* vr = veff ? veff + base : nullptr;
 #pragma unroll
@@ -603,8 +671,12 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             V znext = lz<V>();
             if (z < 7) znext = load_z(io, z + 1);
             if (z < 6) w[z + 14] = load_plane(io, z + 8);
+            if (INMARCH && kb) {
+                if (z + PD + 1 < 8) load_offsets(z + PD + 1);
+                if (z + PD < 8) load_entries(z + PD);
+            }
 
-            const int l = cx + 8 * cy + 64 * z;
+            const int l = lrow + 64 * z;
             V acc = lscale(k.c[0], w[z + 6]);
 #pragma unroll
             for (int s = 1; s <= 6; ++s) {
@@ -617,197 +689,98 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             }
             const V xc = w[z + 6];
             if (vr) acc = lfma(vr[l], xc, acc);
+            if (INMARCH && kb) {
+                // KB term of row z: sum over its entries of h_l beta_lm C_lm
+                const int cnt = e_hi[z] - e_lo[z];
+                static_for<0, 16>([&](auto kc) {
+                    constexpr int kk = decltype(kc)::value;
+                    if (kk < cnt) {
+                        const int sl = row_bcast<kk>(e_slot[z]);
+                        const V* cs = &cst[sl][p][0];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) acc = lfma(row_bcast<kk>(e_b[z][m]), cs[m], acc);
+                    }
+                });
+                for (int en = e_lo[z] + 16; en < e_hi[z]; ++en) {     // rows with more than 16 entries
+                    const T* bb = ent_beta + 4 * int64_t(en);
+                    const V* cs = &cst[ent_slot[en]][p][0];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) acc = lfma(bb[m], cs[m], acc);
+                }
+            }
             V y = lscale(k.alpha, lfma(-k.shift, xc, acc));
             if (Z) y = lfma(-k.beta, zcur, y);
-            r[z] = y;
+            if (KEEP_R) {
+                r[z] = y;
+            } else {
+                const bool in = (bmask[8 * cur_blk + z] >> lrow) & 1;
+                bstore<V>(in ? y : lz<V>(), rY, off_y + unsigned(z) * plane_y);
+            }
             zcur = znext;
             __syncthreads();
         }
 
-        // park the KB coefficients, then prefetch the next tile while the
-        // scatter of this one runs
-        if (STAGE && ent_off) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = t + NT * u;
-                const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
-                if (sl < kMaxBlockAtoms) cst[sl][lp][lm] = cstage[u];
-            }
-        }
-        const int64_t cur_blk = io.blk;
-        const bool cur_vok = io.vok;
-        if (STAGE) __syncthreads();
-
-        // KB scatter for the 8 rows of this column, in rounds so that the
-        // entry loads of all rows are in flight together
-        if (ent_off && cur_vok) {
-            int e0[8], e1[8];
-            int nmax = 0;
-#pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                const int64_t row = base + cx + 8 * cy + 64 * z;
-                e0[z] = ent_off[row];
-                e1[z] = ent_off[row + 1];
-                nmax = max(nmax, e1[z] - e0[z]);
-            }
-            for (int j = 0; j < nmax; ++j) {
+        if (!INMARCH) {
+            // KB scatter after the march (block atom lists too long to stage,
+            // or 8-lane tiles), in rounds so that the entry loads of all rows
+            // are in flight together
+            if (kb && cur_vok) {
+                int e0[8], e1[8];
+                int nmax = 0;
 #pragma unroll
                 for (int z = 0; z < 8; ++z) {
-                    const int en = e0[z] + j;
-                    if (en < e1[z]) {
-                        const T* bb = ent_beta + 4 * int64_t(en);
-                        V c0, c1, c2, c3;
-                        if (STAGE) {
-                            const int sl = ent_slot[en];
-                            c0 = cst[sl][p][0];
-                            c1 = cst[sl][p][1];
-                            c2 = cst[sl][p][2];
-                            c3 = cst[sl][p][3];
-                        } else {
-                            const T* ca = C + int64_t(ent_atom[en]) * 4 * int64_t(nvec) + vbase;
-                            c0 = *reinterpret_cast<const V*>(ca);
-                            c1 = *reinterpret_cast<const V*>(ca + nvec);
-                            c2 = *reinterpret_cast<const V*>(ca + 2 * nvec);
-                            c3 = *reinterpret_cast<const V*>(ca + 3 * nvec);
+                    const int64_t row = base + lrow + 64 * z;
+                    e0[z] = ent_off[row];
+                    e1[z] = ent_off[row + 1];
+                    nmax = max(nmax, e1[z] - e0[z]);
+                }
+                for (int j = 0; j < nmax; ++j) {
+#pragma unroll
+                    for (int z = 0; z < 8; ++z) {
+                        const int en = e0[z] + j;
+                        if (en < e1[z]) {
+                            const T* bb = ent_beta + 4 * int64_t(en);
+                            V c0, c1, c2, c3;
+                            if (STAGE) {
+                                const int sl = ent_slot[en];
+                                c0 = cst[sl][p][0];
+                                c1 = cst[sl][p][1];
+                                c2 = cst[sl][p][2];
+                                c3 = cst[sl][p][3];
+                            } else {
+                                const T* ca = C + int64_t(ent_atom[en]) * 4 * int64_t(nvec) + vbase;
+                                c0 = *reinterpret_cast<const V*>(ca);
+                                c1 = *reinterpret_cast<const V*>(ca + nvec);
+                                c2 = *reinterpret_cast<const V*>(ca + 2 * nvec);
+                                c3 = *reinterpret_cast<const V*>(ca + 3 * nvec);
+                            }
+                            V acc = lscale(bb[0], c0);
+                            acc = lfma(bb[1], c1, acc);
+                            acc = lfma(bb[2], c2, acc);
+                            acc = lfma(bb[3], c3, acc);
+                            r[z] = lfma(k.alpha, acc, r[z]);
                         }
-                        V acc = lscale(bb[0], c0);
-                        acc = lfma(bb[1], c1, acc);
-                        acc = lfma(bb[2], c2, acc);
-                        acc = lfma(bb[3], c3, acc);
-                        r[z] = lfma(k.alpha, acc, r[z]);
                     }
                 }
             }
         }
-        {
-            const __amdgpu_buffer_rsrc_t rY = make_rsrc(Y + base * ldy, unsigned(kBlockPts) * unsigned(ldy) * es);
-            const unsigned off_y = cur_vok ? (unsigned(cx + 8 * cy) * unsigned(ldy) + unsigned(vbase)) * es : kOOB;
+        if (KEEP_R) {
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
-                const bool in = (bmask[8 * cur_blk + z] >> (cx + 8 * cy)) & 1;
+                const bool in = (bmask[8 * cur_blk + z] >> lrow) & 1;
                 bstore<V>(in ? r[z] : lz<V>(), rY, off_y + unsigned(z) * plane_y);
             }
         }
 
-        // Epilogue (EMIT): KB coefficient partials of the output,
-        //   part[q][lm][v] = sum over the support rows of atom a(q) inside
-        //   this block of (h^3 beta_alm(row)) Y(row, v),
-        // one per (block, atom) pair q.  The block's gather entries (pairs in
-        // slot order, rows ascending within a pair) are cut into 64 equal
-        // intervals, one per column group; pairs that straddle an interval
-        // boundary are summed in a second phase, in interval order, so the
-        // result does not depend on scheduling.
-        if (EMIT) {
-            const int q0 = blk_atom_off[cur_blk];
-            const int na = blk_atom_off[cur_blk + 1] - q0;
-            if (na > 0) {
-                V* ylds = &plane[0][0][0];                  // [512][LANES]
-                V* tails = ylds + kBlockPts * LANES;        // [64][4][LANES]
-                int* po = reinterpret_cast<int*>(tails + 256 * LANES);   // [na + 1] local pair starts
-#pragma unroll
-                for (int z = 0; z < 8; ++z) {
-                    const bool in = (bmask[8 * cur_blk + z] >> (cx + 8 * cy)) & 1;
-                    ylds[(col + 64 * z) * LANES + p] = in ? r[z] : lz<V>();
-                }
-                const int64_t e_base = pair_start[q0];
-                for (int i = t; i <= na; i += NT) po[i] = int(pair_start[q0 + i] - e_base);
-                __syncthreads();
-                const int E = po[na];
-                const int L = (E + 63) >> 6;
-                const int j0 = min(col * L, E), j1 = min(j0 + L, E);
-                V hd[4];
-                int s_head = -1;
-                if (j0 < j1) {
-                    int sl = 0;
-                    while (po[sl + 1] <= j0) ++sl;
-                    for (;;) {
-                        const int jb = max(po[sl], j0), je = min(po[sl + 1], j1);
-                        V acc[4];
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) acc[m] = lz<V>();
-                        // the group's LANES lanes load LANES entries at once
-                        // (one memory round trip), then broadcast them in turn
-                        // within the group (a 16-lane row of the wave)
-                        const uint16_t* gr = gat_row + e_base;
-                        const T* gb = gat_beta + 4 * e_base;
-                        for (int jc = jb; jc < je; jc += LANES) {
-                            const int jj = jc + p;
-                            int u_own = 0;
-                            T b_own[4] = {T(0), T(0), T(0), T(0)};
-                            if (jj < je) {
-                                u_own = gr[jj];
-                                load4(gb + 4 * int64_t(jj), b_own);
-                            }
-                            const int cnt = min(LANES, je - jc);
-                            for (int kk = 0; kk < cnt; ++kk) {
-                                const int u = __shfl(u_own, kk, LANES);
-                                const V y = ylds[u * LANES + p];
-#pragma unroll
-                                for (int m = 0; m < 4; ++m) acc[m] = lfma(__shfl(b_own[m], kk, LANES), y, acc[m]);
-                            }
-                        }
-                        const bool before = po[sl] < j0, after = po[sl + 1] > j1;
-                        if (after) {
-#pragma unroll
-                            for (int m = 0; m < 4; ++m) tails[(col * 4 + m) * LANES + p] = acc[m];
-                        } else if (before) {
-                            s_head = sl;
-#pragma unroll
-                            for (int m = 0; m < 4; ++m) hd[m] = acc[m];
-                        } else if (cur_vok) {
-#pragma unroll
-                            for (int m = 0; m < 4; ++m)
-                                *reinterpret_cast<V*>(part + (int64_t(q0 + sl) * 4 + m) * nvec + vbase) = acc[m];
-                        }
-                        if (je == j1) break;
-                        ++sl;
-                    }
-                }
-                __syncthreads();
-                if (s_head >= 0 && cur_vok) {
-                    const int g_first = po[s_head] / L;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        V tot = tails[(g_first * 4 + m) * LANES + p];
-                        for (int g = g_first + 1; g < col; ++g) tot = ladd(tot, tails[(g * 4 + m) * LANES + p]);
-                        tot = ladd(tot, hd[m]);
-                        *reinterpret_cast<V*>(part + (int64_t(q0 + s_head) * 4 + m) * nvec + vbase) = tot;
-                    }
-                }
-            }
-        }
-    }
-}
-
-// C[a][lm][v] = sum of the partials of atom a's (block, atom) pairs, blocks
-// ascending.  One workgroup per atom; 16-byte quads over the 4 * nvec values.
-template <class T>
-__global__ void __launch_bounds__(256) kb_reduce_kernel(const int32_t* __restrict__ apair_off,
-                                                        const int32_t* __restrict__ apair_q, const T* __restrict__ part,
-                                                        int nvec, T* __restrict__ C) {
-    using V = typename Quad<T>::V;
-    constexpr int QN = Quad<T>::N;
-    const int a = blockIdx.x;
-    const int64_t n = 4 * int64_t(nvec);
-    const int k0 = apair_off[a], k1 = apair_off[a + 1];
-    for (int64_t e = int64_t(threadIdx.x) * QN; e < n; e += 256 * QN) {
-        V acc = vzero<V>();
-        for (int k = k0; k < k1; ++k) acc = vadd(acc, *reinterpret_cast<const V*>(part + int64_t(apair_q[k]) * n + e));
-        *reinterpret_cast<V*>(C + int64_t(a) * n + e) = acc;
     }
 }
 
 constexpr int kLanes = 16;
 
-template <class T>
-static const T* gat_beta_of(const chf_ham* H) {
-    return std::is_same<T, double>::value ? H->gat_beta64.as<T>() : H->gat_beta32.as<T>();
-}
-
 template <class T, int LANES>
 static void launch_hx_tiled_l(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz,
                               int nvec, const T* C, double alpha, double shift, double beta, hipStream_t s,
-                              bool lap_only, T* part) {
+                              bool lap_only) {
     constexpr int CH = LANES * Lane<T>::N;
     constexpr int G = 16 / LANES;
     const int n_chunks = (nvec + CH - 1) / CH;
@@ -821,29 +794,19 @@ static void launch_hx_tiled_l(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t
 #define CHF_TILED_ARGS                                                                                              \
     H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,                \
         H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),     \
-        H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef, H->pair_start.as<int64_t>(),             \
-        H->gat_row.as<uint16_t>(), gat_beta_of<T>(H), part
-    if (stage && part)
-        hx_tiled_kernel<T, true, LANES, true><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
-    else if (stage)
-        hx_tiled_kernel<T, true, LANES, false><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
+        H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef
+    if (stage)
+        hx_tiled_kernel<T, true, LANES><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
     else
-        hx_tiled_kernel<T, false, LANES, false><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
+        hx_tiled_kernel<T, false, LANES><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
 #undef CHF_TILED_ARGS
     LAUNCH_CHECK();
 }
 
 template <class T>
 void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
-                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only, T* part) {
-    launch_hx_tiled_l<T, kLanes>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only, part);
-}
-
-template <class T>
-static void launch_kb_reduce(chf_ham* H, const T* part, int nvec, T* C, hipStream_t s) {
-    kb_reduce_kernel<T><<<dim3(unsigned(H->proj.n_proj)), dim3(256), 0, s>>>(
-        H->apair_off.as<int32_t>(), H->apair_q.as<int32_t>(), part, nvec, C);
-    LAUNCH_CHECK();
+                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only) {
+    launch_hx_tiled_l<T, kLanes>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only);
 }
 
 // ---------------------------------------------------------------------------
@@ -852,7 +815,7 @@ static void launch_kb_reduce(chf_ham* H, const T* part, int nvec, T* C, hipStrea
 // ---------------------------------------------------------------------------
 struct KernelTimer {
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[3];   // 0: H X, 1: KB gather, 2: KB partial sums
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[2];   // 0: H X, 1: KB gather
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -904,42 +867,15 @@ bool tiled_ok(const chf_ham* H, const void* X, int64_t ldx, const void* Y, int64
     return true;
 }
 
-// Largest partial-coefficient buffer the fused epilogue may use; beyond it
-// the coefficients come from the standalone gather.
-constexpr size_t kMaxPartBytes = size_t(32) << 30;
-
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only, int kb_flags) {
-    const bool kb = H->proj.n_proj > 0 && !lap_only;
-    const size_t cbytes = size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * sizeof(T);
-    H->kb_coef.ensure(cbytes);
-    const bool reuse = kb && (kb_flags & KB_REUSE) && H->kb_ready == static_cast<const void*>(X) &&
-                       H->kb_ready_ld == ldx && H->kb_ready_nvec == nvec && H->kb_ready_es == int(sizeof(T));
-    H->kb_ready = nullptr;
-    if (kb && !reuse) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, H->kb_coef.as<T>(), s); });
-    const T* C = H->kb_coef.as<T>();
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only) {
+    H->kb_coef.ensure(size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * sizeof(T));
+    T* C = H->kb_coef.as<T>();
+    if (H->proj.n_proj > 0 && !lap_only) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, C, s); });
     const bool tiled = force_kernel != 1 && tiled_ok<T>(H, X, ldx, Y, ldy, Z, ldz, nvec);
     if (tiled) {
-        const size_t pbytes = size_t(H->n_block_pairs) * 4 * size_t(nvec) * sizeof(T);
-        const bool emit = kb && (kb_flags & KB_EMIT) && H->proj.max_block_atoms <= kMaxBlockAtoms &&
-                          gat_beta_of<T>(H) != nullptr && H->n_block_pairs > 0 && pbytes <= kMaxPartBytes;
-        T* part = nullptr;
-        if (emit) {
-            H->kb_part.ensure(pbytes);
-            H->kb_next.ensure(cbytes);
-            part = H->kb_part.as<T>();
-        }
-        timed(0, s, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only, part); });
-        if (emit) {
-            timed(2, s, [&] { launch_kb_reduce<T>(H, part, nvec, H->kb_next.as<T>(), s); });
-            std::swap(H->kb_coef.p, H->kb_next.p);
-            std::swap(H->kb_coef.bytes, H->kb_next.bytes);
-            H->kb_ready = Y;
-            H->kb_ready_ld = ldy;
-            H->kb_ready_nvec = nvec;
-            H->kb_ready_es = int(sizeof(T));
-        }
+        timed(0, s, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
     } else {
         if (!H->has_nbr) fail(CHF_EUNSUPPORTED, "generic H X needs the neighbour table (keep_nbr) for this layout");
         timed(0, s, [&] { launch_hx_generic<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
@@ -953,7 +889,7 @@ void timer_enable(int on) {
 
 void timer_read(double* ms, int64_t* launches) {
     HIP_CHECK(hipDeviceSynchronize());
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < 2; ++w) {
         double t = 0;
         for (auto& p : g_timer.spans[w]) {
             float f = 0;
@@ -966,9 +902,9 @@ void timer_read(double* ms, int64_t* launches) {
 }
 
 template void hx_step<float>(chf_ham*, const float*, int64_t, float*, int64_t, const float*, int64_t, int, double,
-                             double, double, hipStream_t, int, bool, int);
+                             double, double, hipStream_t, int, bool);
 template void hx_step<double>(chf_ham*, const double*, int64_t, double*, int64_t, const double*, int64_t, int,
-                              double, double, double, hipStream_t, int, bool, int);
+                              double, double, double, hipStream_t, int, bool);
 template void launch_kb_gather<float>(chf_ham*, const float*, int64_t, int, float*, hipStream_t);
 template void launch_kb_gather<double>(chf_ham*, const double*, int64_t, int, double*, hipStream_t);
 

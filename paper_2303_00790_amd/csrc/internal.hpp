@@ -138,20 +138,9 @@ struct HostProj {
     std::vector<int32_t> blk_atoms;     // projector-atom indices, ascending per block
     std::vector<uint8_t> ent_slot;      // [pairs]
     int max_block_atoms = 0;
-    // block-major gather list: for every block, for every atom of its list,
-    // the atom's support rows inside the block (ascending) with their values;
-    // (block, atom) pair q = blk_atom_off[b] + slot owns entries
-    // [pair_start[q], pair_start[q + 1])
-    std::vector<int64_t> pair_start;    // [block pairs + 1]
-    std::vector<uint16_t> gat_row;      // [pairs] row index within the block
-    std::vector<double> gat_beta;       // [pairs][4], unscaled
-    // block pairs of every atom, blocks ascending (sums of per-block partials)
-    std::vector<int32_t> apair_off;     // [n_proj + 1]
-    std::vector<int32_t> apair_q;       // [block pairs]
 };
 
 void build_block_atoms(const HostGrid& g, HostProj& P);
-void build_block_gather(const HostGrid& g, HostProj& P);
 
 void build_projectors(const HostGrid& g, const chf_atoms& atoms, const chf_pp& pp, HostProj& out);
 
@@ -186,19 +175,6 @@ struct chf_ham {
     chf::DevBuf sup_beta64, ent_beta64;  // double [pairs][4]
     chf::DevBuf sup_beta32, ent_beta32;  // float  [pairs][4]
     chf::DevBuf kb_coef;        // KB coefficients scratch [4 n_proj][nvec] in the work dtype
-    chf::DevBuf kb_next;        // coefficients of the last fused step's output (same layout)
-    chf::DevBuf kb_part;        // per-(block, atom) partial coefficients [block pairs][4][nvec]
-    chf::DevBuf pair_start;     // int64 [block pairs + 1]
-    chf::DevBuf gat_row;        // uint16 [pairs]
-    chf::DevBuf gat_beta64;     // double [pairs][4], h^3-scaled
-    chf::DevBuf gat_beta32;     // float  [pairs][4], h^3-scaled
-    chf::DevBuf apair_off;      // int32 [n_proj + 1]
-    chf::DevBuf apair_q;        // int32 [block pairs]
-    int64_t n_block_pairs = 0;
-    // output of the last H X step that emitted its KB coefficients (kb_coef)
-    const void* kb_ready = nullptr;
-    int64_t kb_ready_ld = 0;
-    int kb_ready_nvec = 0, kb_ready_es = 0;
     int dtypes = 0;
     bool has_nbr = false;
     // Poisson exterior stencil points (built on first use, scf.hip)

@@ -10,15 +10,10 @@ template <class T>
 void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipStream_t s);
 // Y = alpha (H X - shift X) - beta Z ; Z may be null or alias Y.  force_kernel:
 // 0 = best available, 1 = generic neighbour-table kernel.  lap_only: H is
-// replaced by -1/2 L (no V_eff, no projectors).  kb_flags (recurrences
-// only): KB_EMIT asks the tiled kernel to also produce the KB coefficients
-// of Y; KB_REUSE lets the next step, whose X is that Y, use them instead of
-// gathering again (honoured only when X, ldx, nvec and the type match the
-// last emitting step and no other H X ran in between).
-enum { KB_REUSE = 1, KB_EMIT = 2 };
+// replaced by -1/2 L (no V_eff, no projectors).
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false, int kb_flags = 0);
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false);
 
 void timer_enable(int on);
 void timer_read(double* ms, int64_t* launches);

@@ -662,15 +662,13 @@ static void scf_step_t(chf_scf* S, T* X, int64_t ldx, T* W, int64_t ldw, chf_scf
             const double e = (b - S->a) / 2, c = (b + S->a) / 2;
             const double sigma1 = e / (S->a0 - c);
             double sigma = sigma1;
-            const int m = S->prm.degree;
-            hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, M, sigma1 / e, c, 0.0, s, 0, false, m > 1 ? KB_EMIT : 0);
-            for (int k = 2; k <= m; ++k) {
+            hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, M, sigma1 / e, c, 0.0, s, 0);
+            for (int k = 2; k <= S->prm.degree; ++k) {
                 const double sn = 1.0 / (2.0 / sigma1 - sigma);
-                const int fl = KB_REUSE | (k < m ? KB_EMIT : 0);
                 if (k % 2 == 0)
-                    hx_step<T>(H, W, ldw, X, ldx, X, ldx, M, 2.0 * sn / e, c, sigma * sn, s, 0, false, fl);
+                    hx_step<T>(H, W, ldw, X, ldx, X, ldx, M, 2.0 * sn / e, c, sigma * sn, s, 0);
                 else
-                    hx_step<T>(H, X, ldx, W, ldw, W, ldw, M, 2.0 * sn / e, c, sigma * sn, s, 0, false, fl);
+                    hx_step<T>(H, X, ldx, W, ldw, W, ldw, M, 2.0 * sn / e, c, sigma * sn, s, 0);
                 sigma = sn;
             }
             if (S->prm.degree % 2 == 1)

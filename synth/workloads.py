@@ -21,11 +21,11 @@ class ModelPP:
     projectors on Si stand in)."""
     z_si: float = 4.0
     z_h: float = 1.0
-    r_loc: float = 0.9       # erf width of the Si local part (bohr)
+    r_loc: float = 0.7       # erf width of the Si local part (bohr)
     r_loc_h: float = 0.5     # erf width of the H local part (bohr)
     r_c: float = 1.2         # Gaussian projector width (bohr)
     r_cut: float = 4.8       # projector cutoff (bohr)
-    h_s: float = 2.0         # KB energy, s channel (Ha)
+    h_s: float = 3.0         # KB energy, s channel (Ha)
     h_p: float = 0.0         # KB energy, p channel (Ha)
 
 
