@@ -1,10 +1,12 @@
 // C ABI: handles, argument validation, error model, and the Hamiltonian /
 // filter entry points.  Every entry point catches everything and returns a
 // status code; chf_last_error() holds the message.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <type_traits>
 
@@ -200,33 +202,66 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
         // projectors
         build_projectors(g, *atoms, *pp, H->proj);
         HostProj& P = H->proj;
-        upload(H->sup_off, P.sup_off, s);
-        upload(H->sup_row, P.sup_row, s);
-        upload(H->ent_off, P.ent_off, s);
         CHF_REQUIRE(P.sup_row.size() < (size_t(1) << 31), "ham_build: more than 2^31 projector pairs");
+        if (gd->ordering == CHF_ORDER_HILBERT) build_block_atoms(g, H->proj);
+        // Device order of the projector atoms (the layout of the KB
+        // coefficients and of the gather's work): by the first row of their
+        // support, so that atoms next to each other in that order are close
+        // along the Hilbert curve and share support rows in L2.  The host
+        // tables keep the input order.
+        const int64_t np = P.n_proj;
+        std::vector<int32_t> perm(static_cast<size_t>(np)), inv(static_cast<size_t>(np));
+        for (int64_t a = 0; a < np; ++a) perm[size_t(a)] = int32_t(a);
+        auto first_row = [&](int32_t a) {
+            return P.sup_off[size_t(a)] < P.sup_off[size_t(a) + 1] ? P.sup_row[size_t(P.sup_off[size_t(a)])]
+                                                                  : std::numeric_limits<int32_t>::max();
+        };
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return first_row(x) < first_row(y); });
+        for (int64_t i = 0; i < np; ++i) inv[size_t(perm[size_t(i)])] = int32_t(i);
+        std::vector<double> sup_beta_dev;
+        {
+            std::vector<int64_t> off(static_cast<size_t>(np) + 1, 0);
+            std::vector<int32_t> rows;
+            rows.reserve(P.sup_row.size());
+            sup_beta_dev.reserve(P.sup_beta.size());
+            for (int64_t i = 0; i < np; ++i) {
+                const int32_t a = perm[size_t(i)];
+                const int64_t j0 = P.sup_off[size_t(a)], j1 = P.sup_off[size_t(a) + 1];
+                rows.insert(rows.end(), P.sup_row.begin() + j0, P.sup_row.begin() + j1);
+                sup_beta_dev.insert(sup_beta_dev.end(), P.sup_beta.begin() + 4 * j0, P.sup_beta.begin() + 4 * j1);
+                off[size_t(i) + 1] = off[size_t(i)] + (j1 - j0);
+            }
+            upload(H->sup_off, off, s);
+            upload(H->sup_row, rows, s);
+        }
+        upload(H->ent_off, P.ent_off, s);
         {
             std::vector<int32_t> off32(P.ent_off.begin(), P.ent_off.end());
             upload(H->ent_off32, off32, s);
+            std::vector<int32_t> ea(P.ent_atom.size());
+            for (size_t e = 0; e < ea.size(); ++e) ea[e] = inv[size_t(P.ent_atom[e])];
+            upload(H->ent_atom, ea, s);
         }
-        upload(H->ent_atom, P.ent_atom, s);
         if (gd->ordering == CHF_ORDER_HILBERT) {
-            build_block_atoms(g, H->proj);
             upload(H->ent_slot, H->proj.ent_slot, s);
             std::vector<int32_t> off32(H->proj.blk_atom_off.begin(), H->proj.blk_atom_off.end());
             upload(H->blk_atom_off, off32, s);
-            upload(H->blk_atoms, H->proj.blk_atoms, s);
+            std::vector<int32_t> ba(H->proj.blk_atoms.size());
+            for (size_t i = 0; i < ba.size(); ++i) ba[i] = inv[size_t(H->proj.blk_atoms[i])];
+            upload(H->blk_atoms, ba, s);
         }
         const double h3 = gd->h * gd->h * gd->h;
         const double gsc[4] = {h3, h3, h3, h3};
         const double ssc[4] = {pp->h_s, pp->h_p, pp->h_p, pp->h_p};
         if (gd->dtypes & 2) {
-            upload(H->sup_beta64, cast_scaled<double>(P.sup_beta, gsc), s);
+            upload(H->sup_beta64, cast_scaled<double>(sup_beta_dev, gsc), s);
             upload(H->ent_beta64, cast_scaled<double>(P.ent_beta, ssc), s);
         }
         if (gd->dtypes & 1) {
-            upload(H->sup_beta32, cast_scaled<float>(P.sup_beta, gsc), s);
+            upload(H->sup_beta32, cast_scaled<float>(sup_beta_dev, gsc), s);
             upload(H->ent_beta32, cast_scaled<float>(P.ent_beta, ssc), s);
         }
+        HIP_CHECK(hipStreamSynchronize(s));   // host staging vectors above go out of scope
         // local potential (FP64, all atoms)
         H->vloc.alloc(size_t(g.n_rows) * 8);
         if (gd->dtypes & 2) H->veff64.alloc(size_t(g.n_rows) * 8);

@@ -68,7 +68,6 @@ void dot_device(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, i
 
 template <class T>
 double dot_host(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, int64_t incy, hipStream_t s) {
-    ctx->info.ensure(64);
     double* d = reinterpret_cast<double*>(ctx->info.p);
     dot_device<T>(ctx, n, x, incx, y, incy, d, s);
     double h = 0;
@@ -386,7 +385,6 @@ static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, d
     double* S = mm_scratch(ctx, m, 0);
     gram_product<T>(ctx, X, ldx, X, ldx, n_rows, m, m, S, m, s);
     if (shift_rel > 0) {
-        ctx->info.ensure(64);
         double* tr = reinterpret_cast<double*>(ctx->info.p);
         trace_kernel<<<1, 256, 0, s>>>(m, S, tr);
         double htr = 0;
@@ -548,6 +546,13 @@ int chf_ctx_create(int device, chf_ctx** out) {
         if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
             delete c;
             fail(CHF_EHIP, "rocblas_create_handle failed");
+        }
+        try {
+            c->info.alloc(kInfoBytes);   // device scalars and the mixing coefficients
+        } catch (...) {
+            rocblas_destroy_handle(c->blas);
+            delete c;
+            throw;
         }
         *out = c;
         return CHF_OK;

@@ -256,11 +256,16 @@ template <class T>
 __global__ void __launch_bounds__(256) kb_gather_kernel(const int64_t* __restrict__ sup_off,
                                                         const int32_t* __restrict__ sup_row,
                                                         const T* __restrict__ sup_beta, const T* __restrict__ X,
-                                                        int64_t ldx, int nvec, T* __restrict__ C) {
+                                                        int64_t ldx, int nvec, T* __restrict__ C, int n_proj) {
     using V = typename Quad<T>::V;
     constexpr int QN = Quad<T>::N;
     __shared__ V part[4][4][64];
-    const int a = blockIdx.x;
+    // XCD-aware order (grid = 8 * per_xcd): consecutive atoms, which share
+    // support rows (the device numbers atoms along the Hilbert curve), run on
+    // the same XCD and read the shared rows from its L2
+    const int per_xcd = int(gridDim.x / 8);
+    const int a = int(blockIdx.x % 8) * per_xcd + int(blockIdx.x / 8);
+    if (a >= n_proj) return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int v = (blockIdx.y * 64 + lane) * QN;
@@ -347,9 +352,9 @@ void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipSt
     constexpr int QN = Quad<T>::N;
     const T* beta = std::is_same<T, double>::value ? H->sup_beta64.as<T>() : H->sup_beta32.as<T>();
     if (nvec % QN == 0 && ldx % QN == 0 && uintptr_t(X) % 16 == 0) {
-        dim3 grid(unsigned(H->proj.n_proj), unsigned((nvec / QN + 63) / 64));
+        dim3 grid(unsigned(8 * ((H->proj.n_proj + 7) / 8)), unsigned((nvec / QN + 63) / 64));
         kb_gather_kernel<T><<<grid, dim3(256), 0, s>>>(H->sup_off.as<int64_t>(), H->sup_row.as<int32_t>(), beta, X, ldx,
-                                                       nvec, C);
+                                                       nvec, C, int(H->proj.n_proj));
     } else {
         dim3 grid(unsigned(H->proj.n_proj), unsigned((nvec + 63) / 64));
         kb_gather_scalar_kernel<T><<<grid, dim3(256), 0, s>>>(H->sup_off.as<int64_t>(), H->sup_row.as<int32_t>(), beta,

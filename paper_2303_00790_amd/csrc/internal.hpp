@@ -185,6 +185,11 @@ struct chf_ham {
     hipStream_t stream = nullptr;  // stream of the last call (for destroy)
 };
 
+// bytes of chf_ctx::info, allocated with the context: a few device scalars
+// (reduction results, factorisation status) and up to 32 Anderson
+// coefficients
+constexpr size_t kInfoBytes = 4096;
+
 struct chf_ctx {
     int device = 0;
     rocblas_handle blas = nullptr;

@@ -379,7 +379,6 @@ int hartree_solve(chf_ham* H, chf_ctx* ctx, const double* rho, double* vh, doubl
     double* M = vg + std::max<int64_t>(1, H->n_ghost);
     double* ck = M + 64;
     ctx->red.ensure(size_t(1024) * kNMom * sizeof(double));
-    ctx->info.ensure(64);
     static bool exp_ready = false;
     if (!exp_ready) {
         int e[kNMom][3];
@@ -614,7 +613,6 @@ static double wsum_host(chf_ctx* ctx, int64_t n, const double* w, const double* 
                         const double* d, hipStream_t s) {
     const int nb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)));
     ctx->red.ensure(size_t(nb) * sizeof(double));
-    ctx->info.ensure(64);
     wdiff2_kernel<<<nb, 256, 0, s>>>(n, w, a, b, c, d, ctx->red.as<double>());
     LAUNCH_CHECK();
     return sum_host(ctx, nb, s);
