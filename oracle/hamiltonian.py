@@ -167,3 +167,89 @@ def build_hamiltonian(g: Grid, pos: np.ndarray, species: np.ndarray, pp: PseudoP
     vloc = local_potential(g, pos, species, pp) if with_vloc else np.zeros(g.n)
     B, e = projector_matrix(g, pos, species, pp)
     return Hamiltonian(g, lap, vloc, vloc.copy(), B, e)
+
+
+def apply_at_points(ijk: np.ndarray, x_at, h: float, radius: float, pos: np.ndarray, species: np.ndarray,
+                    pp: PseudoParams, veff: np.ndarray | None = None) -> np.ndarray:
+    """(H X)(p) at the integer grid points ``ijk`` [P, 3], one point at a time,
+    for sizes where the whole-grid operator cannot be assembled.
+
+    ``x_at(pts)`` returns the rows of X [len(pts), M] at integer points
+    ``pts`` that lie inside the sphere (the caller's layout lookup).  The
+    terms are the definitions above: the 37-point star of -1/2 L with zero
+    values outside the sphere, V_eff (V_loc when ``veff`` is None) times X,
+    and for every Si atom within r_cut of p the KB term
+    sum_lm h_l beta_alm(p) C_alm with C_alm = h^3 sum_q beta_alm(q) X(q) over
+    the atom's support points q inside the sphere.
+    Returns (HX [P, M], magnitude [P, M]): the second is the sum of the
+    absolute values of the terms, the scale of the rounding error of any
+    evaluation of the same sum.
+    """
+    n_r = int(math.floor(radius / h))
+    thr = math.floor((radius / h) ** 2 + 1e-9)
+
+    def inside(p):
+        return (p * p).sum(axis=-1) <= thr
+
+    c = fd_coefficients() / (h * h)
+    n_s = math.sqrt(4.0 / (math.sqrt(math.pi) * pp.r_c ** 3))
+    n_p = math.sqrt(8.0 / (3.0 * math.sqrt(math.pi) * pp.r_c ** 5))
+    y00 = 1.0 / math.sqrt(4.0 * math.pi)
+    y1 = math.sqrt(3.0 / (4.0 * math.pi))
+    si = np.nonzero(species == 0)[0]
+    z = pp.charges(species)
+    w = pp.widths(species)
+    kcut = int(math.ceil(pp.r_cut / h)) + 1
+    out, mag = [], []
+    for p in np.asarray(ijk, dtype=np.int64):
+        xp = x_at(p[None])[0]
+        y = np.zeros_like(xp, dtype=np.float64)
+        a_sum = np.zeros_like(y)
+        # -1/2 L: centre weight appears once per axis
+        y += -0.5 * 3.0 * c[0] * xp
+        a_sum += abs(1.5 * c[0]) * np.abs(xp)
+        for axis in range(3):
+            for k in range(1, HALF_ORDER + 1):
+                for sgn in (-1, 1):
+                    q = p.copy()
+                    q[axis] += sgn * k
+                    if inside(q):
+                        xq = x_at(q[None])[0]
+                        y += -0.5 * c[k] * xq
+                        a_sum += abs(0.5 * c[k]) * np.abs(xq)
+        r = p.astype(np.float64) * h
+        if veff is None:
+            d = np.sqrt(((pos - r) ** 2).sum(axis=1))
+            small = d < 1e-8
+            dd = np.where(small, 1.0, d)
+            v = -float(np.where(small, 2.0 * z / (math.sqrt(math.pi) * w), z * erf(dd / w) / dd).sum())
+        else:
+            v = float(veff)
+        y += v * xp
+        a_sum += abs(v) * np.abs(xp)
+        for a in si:
+            dv = r - pos[a]
+            if float(dv @ dv) > pp.r_cut ** 2:
+                continue
+            # the atom's support: grid points within r_cut of it, inside the sphere
+            ca = np.round(pos[a] / h).astype(np.int64)
+            g = np.arange(-kcut, kcut + 1)
+            gi, gj, gk = np.meshgrid(g, g, g, indexing="ij")
+            pts = np.stack([gi.ravel(), gj.ravel(), gk.ravel()], axis=1) + ca
+            rel = pts.astype(np.float64) * h - pos[a]
+            d2 = (rel * rel).sum(axis=1)
+            keep = (d2 <= pp.r_cut ** 2) & inside(pts)
+            pts, rel, d2 = pts[keep], rel[keep], d2[keep]
+            gq = np.exp(-d2 / (2.0 * pp.r_c ** 2))
+            bq = np.stack([n_s * y00 * gq, n_p * y1 * gq * rel[:, 0], n_p * y1 * gq * rel[:, 1],
+                           n_p * y1 * gq * rel[:, 2]], axis=1)
+            xq = x_at(pts)
+            cq = h ** 3 * (bq.T @ xq)
+            gp = math.exp(-float(dv @ dv) / (2.0 * pp.r_c ** 2))
+            bp = np.array([n_s * y00 * gp, n_p * y1 * gp * dv[0], n_p * y1 * gp * dv[1], n_p * y1 * gp * dv[2]])
+            hl = np.array([pp.h_s, pp.h_p, pp.h_p, pp.h_p])
+            y += (bp * hl) @ cq
+            a_sum += np.abs(bp * hl) @ (h ** 3 * (np.abs(bq).T @ np.abs(xq)))
+        out.append(y)
+        mag.append(a_sum)
+    return np.array(out), np.array(mag)

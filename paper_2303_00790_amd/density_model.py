@@ -40,12 +40,12 @@ def box_geometry(H) -> tuple[int, int]:
     return D, n_r + (D - (2 * n_r + 1)) // 2
 
 
-def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, max_steps: int = 60):
+def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, max_steps: int = 60, log=None):
     import torch
     st = S.setup(cluster, pp, dtype=dtype)
     H = st["H"]
     rho_sad = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
-    res = S.run(st, rho_sad.clone(), max_steps=max_steps, sre_tol_ry=sre_tol_ry)
+    res = S.run(st, rho_sad.clone(), max_steps=max_steps, sre_tol_ry=sre_tol_ry, log=log)
     rho_conv = torch.zeros_like(rho_sad)
     st["scf"].fields(rho_conv)
     D, off = box_geometry(H)
@@ -66,7 +66,7 @@ def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: fl
         if c.n_atoms == 0:
             continue
         t0 = time.perf_counter()
-        smp, res = converged_sample(c, pp)
+        smp, res = converged_sample(c, pp, log=log)
         data.append(smp)
         log(f"train cluster {i}: d={d:.2f} nm Si{c.n_si}H{c.n_h} box {smp.D}^3 scf steps {res.steps} "
             f"converged {res.converged} ({time.perf_counter() - t0:.1f} s)")
@@ -118,10 +118,12 @@ def evaluate(net, clusters, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, lo
     for c in clusters:
         st = S.setup(c, pp, dtype=dtype)
         rho_sad, rho0 = predicted_start(net, st["H"], c)
-        r_sad = S.run(st, rho_sad, max_steps=80, sre_tol_ry=sre_tol_ry)
+        log(f"eval Si{c.n_si}H{c.n_h}: from the superposition start")
+        r_sad = S.run(st, rho_sad, max_steps=80, sre_tol_ry=sre_tol_ry, log=log)
         st2 = S.setup(c, pp, dtype=dtype)
         _, rho0b = predicted_start(net, st2["H"], c)
-        r_net = S.run(st2, rho0b, max_steps=80, sre_tol_ry=sre_tol_ry)
+        log(f"eval Si{c.n_si}H{c.n_h}: from the learned start")
+        r_net = S.run(st2, rho0b, max_steps=80, sre_tol_ry=sre_tol_ry, log=log)
         row = dict(n_atoms=c.n_atoms, steps_sad=r_sad.steps, steps_net=r_net.steps, conv_sad=r_sad.converged,
                    conv_net=r_net.converged, e_sad=r_sad.energy, e_net=r_net.energy,
                    de_per_atom=abs(r_sad.energy - r_net.energy) / c.n_atoms,

@@ -29,7 +29,8 @@ def converge(cluster, pp, h: float, dtype: str, degree: int, log):
     H = st["H"]
     rho = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
     t0 = time.perf_counter()
-    res = S.run(st, rho, max_steps=80, sre_tol_ry=1e-4)
+    log(f"cluster Si{cluster.n_si}H{cluster.n_h}, h = {h}: {H.n_points} points, {st['M']} states")
+    res = S.run(st, rho, max_steps=80, sre_tol_ry=1e-4, log=log)
     dt = time.perf_counter() - t0
     out = dict(n_points=H.n_points, M=st["M"], n_occ=cluster.n_electrons // 2, steps=res.steps,
                converged=res.converged, energy=res.energy, eig=np.asarray(res.eig, dtype=np.float64), seconds=dt)

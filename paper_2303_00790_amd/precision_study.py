@@ -28,7 +28,7 @@ def run_one(cluster, pp, dtype: str, degree: int, log):
     rho = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = S.run(st, rho, max_steps=80, sre_tol_ry=1e-4)
+    res = S.run(st, rho, max_steps=80, sre_tol_ry=1e-4, log=log)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"{dtype}: {res.steps} SCF steps, converged {res.converged}, E = {res.energy:.10f} Ha, {dt:.1f} s")

@@ -58,7 +58,9 @@ def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nve
     return dict(H=H, ctx=ctx, prm=prm, X=X, W=torch.zeros_like(X), v0=v0, rows=rows, ne=ne, M=M)
 
 
-def run(state, rho0, max_steps: int = 60, sre_tol_ry: float = 1e-4, min_steps: int = 1) -> ScfResult:
+def run(state, rho0, max_steps: int = 60, sre_tol_ry: float = 1e-4, min_steps: int = 1, log=None) -> ScfResult:
+    """SCF steps until SRE < sre_tol_ry; ``log`` (optional) receives one
+    line per step."""
     scf = B.Scf(state["H"], state["ctx"], state["prm"], rho0, state["v0"])
     reps = []
     eig = None
@@ -66,6 +68,8 @@ def run(state, rho0, max_steps: int = 60, sre_tol_ry: float = 1e-4, min_steps: i
     for _ in range(max_steps):
         rep, eig = scf.step(state["X"], state["W"])
         reps.append(rep.as_dict())
+        if log is not None:
+            log(f"  scf step {rep.step}: SRE {rep.sre_ry:.3e} Ry, E {rep.energy:.8f} Ha")
         if rep.sre_ry < sre_tol_ry and rep.step >= min_steps:
             converged = True
             break

@@ -1,0 +1,99 @@
+"""Parity at the full benchmark size: the 16 nm cluster (49,925,477 points,
+256 FP32 vectors, the tiled kernel and launch configuration the benchmark
+times), on sampled rows that the oracle evaluates one point at a time, and
+the first degree step of the filter against H X on the same rows.
+
+Tolerance: every output is a sum of at most a few thousand FP32 products
+(the 37-point star, V X, and the KB term whose coefficients sum ~1350
+support rows); the error of such a sum is bounded by a multiple of the unit
+roundoff (6e-8) times the sum of the absolute values of its terms, which the
+oracle returns beside each value; 3e-5 of that magnitude (500 roundoffs) is
+the bound used."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full_size():
+    from paper_2303_00790_amd import binding as B
+    from synth.cluster import make_cluster
+    from synth.workloads import MODEL_PP, WORKLOADS
+    wl = WORKLOADS["d16nm"]
+    c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
+    radius = c.domain_radius()
+    print(f"case: 16 nm cluster, {wl.nvec} FP32 vectors", flush=True)
+    H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, B.ORDER_HILBERT, keep_nbr=False, dtypes=1)
+    ijk, rows, _ = H.export_ordering()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl.x_seed)
+    X = torch.randn((H.n_rows, wl.nvec), generator=gen, dtype=torch.float32, device="cuda")
+    inside = torch.zeros(H.n_rows, dtype=torch.bool, device="cuda")
+    inside[torch.from_numpy(rows).cuda()] = True
+    X.mul_(inside[:, None])
+    del inside
+    n_r = int(np.abs(ijk).max())
+    D = 2 * n_r + 1
+    keys = ((ijk[:, 0].astype(np.int64) + n_r) * D + (ijk[:, 1] + n_r)) * D + (ijk[:, 2] + n_r)
+    order = np.argsort(keys)
+    skeys = keys[order]
+
+    def rows_of(pts):
+        pts = np.asarray(pts, dtype=np.int64)
+        k = ((pts[:, 0] + n_r) * D + (pts[:, 1] + n_r)) * D + (pts[:, 2] + n_r)
+        at = np.searchsorted(skeys, k)
+        assert np.all(skeys[at] == k)
+        return rows[order[at]]
+
+    def x_at(pts):
+        return X[torch.from_numpy(rows_of(pts)).cuda()].double().cpu().numpy()
+
+    rng = np.random.default_rng(7)
+    r2 = (ijk.astype(np.int64) ** 2).sum(axis=1)
+    si = np.nonzero(c.species == 0)[0]
+    # random points, the outermost points of the sphere, the centre, and
+    # grid points at Si nuclei (inside several projector supports)
+    sample = np.concatenate([rng.choice(len(ijk), 20, replace=False), np.argsort(r2)[-4:], [int(np.argmin(r2))]])
+    at_nuclei = np.round(c.pos[rng.choice(si, 4, replace=False)] / wl.h).astype(np.int64)
+    pts = np.concatenate([ijk[sample].astype(np.int64), at_nuclei])
+    return dict(B=B, H=H, X=X, c=c, wl=wl, radius=radius, pp=MODEL_PP, pts=pts, rows_of=rows_of, x_at=x_at)
+
+
+def _oracle(fs):
+    from oracle import hamiltonian as OH
+    pp = OH.PseudoParams(**dataclasses.asdict(fs["pp"]))
+    return OH.apply_at_points(fs["pts"], fs["x_at"], fs["wl"].h, fs["radius"], fs["c"].pos, fs["c"].species, pp)
+
+
+def test_hx_full_size_sampled_rows(full_size):
+    fs = full_size
+    Y = torch.empty_like(fs["X"])
+    fs["H"].apply(fs["X"], Y)
+    got = Y[torch.from_numpy(fs["rows_of"](fs["pts"])).cuda()].double().cpu().numpy()
+    del Y
+    ref, mag = _oracle(fs)
+    err = np.abs(got - ref)
+    assert np.all(err <= 3e-5 * mag), float((err / mag).max())
+
+
+def test_filter_first_step_full_size(full_size):
+    # degree 1 of the scaled recurrence: Y = (sigma_1 / e)(H X - c X) with
+    # e = (b - a) / 2, c = (b + a) / 2, sigma_1 = e / (a0 - c)
+    fs = full_size
+    a0, a, b = -3.0, -1.0, 40.0
+    e, cc = (b - a) / 2, (b + a) / 2
+    s1 = e / (a0 - cc)
+    Xf = fs["X"].clone()
+    W = torch.empty_like(Xf)
+    fs["H"].filter(Xf, W, 1, a, b, a0)
+    got = Xf[torch.from_numpy(fs["rows_of"](fs["pts"])).cuda()].double().cpu().numpy()
+    del Xf, W
+    hx, mag = _oracle(fs)
+    x = fs["x_at"](fs["pts"])
+    ref = (s1 / e) * (hx - cc * x)
+    bound = abs(s1 / e) * (mag + abs(cc) * np.abs(x))
+    assert np.all(np.abs(got - ref) <= 3e-5 * bound)

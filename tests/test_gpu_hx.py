@@ -160,3 +160,42 @@ def test_invalid_arguments_rejected(system):
     with pytest.raises(B.ChfError) as e:
         s["Hg"].set_veff(bad)
     assert e.value.code == -6
+
+
+def test_empty_block_rejected(system):
+    # no vectors (nvec = 0) and a leading dimension below nvec are invalid
+    s = system
+    B = s["B"]
+    X = torch.zeros((s["Hg"].n_rows, 8), dtype=torch.float64, device="cuda")
+    Y = torch.zeros_like(X)
+    with pytest.raises(B.ChfError) as e:
+        B.call("ham_apply", s["Hg"].handle, B.CHF_F64, B._ptr(X), 8, B._ptr(Y), 8, 0, B._stream())
+    assert e.value.code == -1
+    with pytest.raises(B.ChfError) as e:
+        B.call("ham_apply", s["Hg"].handle, B.CHF_F64, B._ptr(X), 4, B._ptr(Y), 8, 8, B._stream())
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("species", ["none", "hydrogen"])
+def test_no_projector_atoms(species):
+    # degenerate Hamiltonians: no atoms at all (H = -1/2 L) and hydrogen only
+    # (local potential, no KB term), both kernels
+    from paper_2303_00790_amd import binding as B
+    if species == "none":
+        pos, spc = np.zeros((0, 3)), np.zeros(0, np.int32)
+    else:
+        pos, spc = np.array([[0.0, 0.0, 0.7], [0.0, 0.0, -0.7]]), np.ones(2, np.int32)
+    pp = OH.PseudoParams(h_s=2.0, h_p=0.5)
+    radius = 6.0
+    g = G.build_grid(radius, H_SPACING)
+    Ho = OH.build_hamiltonian(g, pos, spc, pp)
+    Hg = B.Hamiltonian(pos, spc, pp, H_SPACING, radius, B.ORDER_HILBERT, keep_nbr=True)
+    rows = torch.from_numpy(g.row_of_rank).cuda()
+    X = random_block(g.n, 16, 2400)
+    Xg = torch.zeros((Hg.n_rows, 16), dtype=torch.float64, device="cuda")
+    Xg[rows] = torch.from_numpy(X).cuda()
+    ref = Ho.apply(X)
+    for generic in (False, True):
+        Yg = torch.full_like(Xg, float("nan"))
+        Hg.apply(Xg, Yg, generic=generic)
+        assert relerr(Yg[rows].cpu().numpy(), ref) < 1e-12

@@ -12,6 +12,7 @@ from scipy.special import erf
 
 from oracle import grid as G
 from oracle import hamiltonian as OH
+from synth.cluster import make_cluster, random_block
 
 
 def test_fd_exact_rationals():
@@ -151,3 +152,25 @@ def test_apply_matches_dense():
     H = OH.build_hamiltonian(g, pos, species, PP_TEST)
     X = np.random.default_rng(2).standard_normal((g.n, 5))
     assert np.allclose(H.apply(X), H.dense() @ X, rtol=0, atol=1e-11)
+
+
+def test_pointwise_apply_matches_grid_operator():
+    # the point-at-a-time evaluation (used for the full-size sampled parity)
+    # against the assembled operator on a small grid, including points on
+    # the sphere's surface and next to atoms
+    c = make_cluster(4.8, 5)
+    g = G.build_grid(c.domain_radius(), 0.9)
+    H = OH.build_hamiltonian(g, c.pos, c.species, PP_TEST)
+    X = random_block(g.n, 3, 1)
+    Y = H.apply(X)
+    key = {tuple(v): i for i, v in enumerate(g.ijk)}
+
+    def x_at(pts):
+        return np.array([X[key[tuple(p)]] for p in pts])
+
+    r2 = (g.ijk ** 2).sum(axis=1)
+    near_atom = np.argmin(((g.xyz[:, None, :] - c.pos[None, c.species == 0, :]) ** 2).sum(axis=2), axis=0)
+    idx = np.concatenate([np.random.default_rng(0).choice(g.n, 12, replace=False), np.argsort(r2)[-6:], near_atom[:6]])
+    ya, mag = OH.apply_at_points(g.ijk[idx], x_at, g.h, g.radius, c.pos, c.species, PP_TEST)
+    assert np.abs(ya - Y[idx]).max() < 1e-12 * np.abs(Y).max()
+    assert np.all(mag >= np.abs(ya) - 1e-12)
