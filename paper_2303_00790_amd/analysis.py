@@ -60,11 +60,22 @@ def gap_ev(eig_ha, n_occ: int) -> float:
     return float((e[n_occ] - e[n_occ - 1]) * HARTREE_EV)
 
 
-def fit_gap(d_nm, gap, p0=(0.5, 4.0, 1.5)):
-    """Least-squares fit of gap(d) = E0 + A / d^k; returns (E0, A, k, R^2)."""
-    from scipy.optimize import curve_fit
+def fit_gap(d_nm, gap, p0=(0.5, 4.0, 1.5), k: float | None = None):
+    """Least-squares fit of gap(d) = E0 + A / d^k; returns (E0, A, k, R^2).
+    With ``k`` given only E0 and A are fitted (a linear least-squares
+    problem in 1 / d^k)."""
     d = np.asarray(d_nm, dtype=np.float64)
     g = np.asarray(gap, dtype=np.float64)
+    if k is not None:
+        if d.size < 2:
+            raise ValueError("need at least two sizes for a two-parameter fit")
+        A_mat = np.stack([np.ones_like(d), d ** -float(k)], axis=1)
+        (e0, a), *_ = np.linalg.lstsq(A_mat, g, rcond=None)
+        res = g - A_mat @ np.array([e0, a])
+        ss_tot = float(((g - g.mean()) ** 2).sum())
+        r2 = 1.0 - float((res ** 2).sum()) / ss_tot if ss_tot > 0 else 1.0
+        return float(e0), float(a), float(k), r2
+    from scipy.optimize import curve_fit
     if d.size < 3:
         raise ValueError("need at least three sizes for a three-parameter fit")
 

@@ -53,8 +53,13 @@ def main(argv=None):
     ap.add_argument("--h2", type=float, default=None)
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--degree", type=int, default=12)
+    ap.add_argument("--pp", default="", help="model pseudopotential overrides, e.g. r_loc=0.9,h_s=2.0")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    pp = MODEL_PP
+    if args.pp:
+        import dataclasses
+        pp = dataclasses.replace(MODEL_PP, **{k: float(v) for k, v in (kv.split("=") for kv in args.pp.split(","))})
 
     def log(msg):
         print(msg, flush=True)
@@ -62,13 +67,13 @@ def main(argv=None):
     rows = []
     for i, d in enumerate(args.diam):
         c = make_cluster(5.0 * d, 30000 + i, sigma_angstrom=0.02)
-        r = converge(c, MODEL_PP, args.h, args.dtype, args.degree, log)
+        r = converge(c, pp, args.h, args.dtype, args.degree, log)
         row = dict(diam_nm=d, n_si=c.n_si, n_h=c.n_h, n_points=r["n_points"], states=r["M"], n_occ=r["n_occ"],
                    steps=r["steps"], converged=r["converged"], energy=r["energy"], seconds=r["seconds"],
                    gap_ev=A.gap_ev(r["eig"], r["n_occ"]))
         _, dens = A.dos_histogram(r["eig"], r["n_occ"])
         if args.h2:
-            r2 = converge(c, MODEL_PP, args.h2, args.dtype, args.degree, log)
+            r2 = converge(c, pp, args.h2, args.dtype, args.degree, log)
             _, dens2 = A.dos_histogram(r2["eig"], r2["n_occ"])
             occ = slice(0, r["n_occ"])
             e1 = (r["eig"][occ] - r["eig"][r["n_occ"] - 1]) * A.HARTREE_EV
@@ -79,11 +84,16 @@ def main(argv=None):
                        occ_shift_max_abs_ev=float(np.max(np.abs(e1 - e2))))
         log(json.dumps(row))
         rows.append(row)
-    res = dict(h=args.h, dtype=args.dtype, clusters=rows)
+    import dataclasses
+    res = dict(h=args.h, dtype=args.dtype, pp=dataclasses.asdict(pp), clusters=rows)
     if len(rows) >= 3:
-        e0, a, k, r2 = A.fit_gap([r["diam_nm"] for r in rows], [r["gap_ev"] for r in rows])
+        dd, gg = [r["diam_nm"] for r in rows], [r["gap_ev"] for r in rows]
+        e0, a, k, r2 = A.fit_gap(dd, gg)
         res["fit"] = dict(e0_ev=e0, a_ev=a, k=k, r2=r2)
         log(f"gap fit: E0 = {e0:.3f} eV, A = {a:.3f} eV, k = {k:.3f}, R^2 = {r2:.5f}")
+        e0, a, k, r2 = A.fit_gap(dd, gg, k=1.56)
+        res["fit_k_1.56"] = dict(e0_ev=e0, a_ev=a, k=k, r2=r2)
+        log(f"gap fit at the published exponent 1.56: E0 = {e0:.3f} eV, A = {a:.3f} eV, R^2 = {r2:.5f}")
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)

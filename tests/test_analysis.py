@@ -50,3 +50,10 @@ def test_dos_rms():
     a = np.array([1.0, 2.0, 3.0])
     assert A.dos_rms(a, a) == 0.0
     assert A.dos_rms(a, a + 1) == pytest.approx(1.0)
+
+
+def test_fixed_exponent_fit():
+    d = np.array([1.0, 2.0, 3.0, 4.0])
+    g = 0.46 + 4.64 / d ** 1.56
+    e0, a, k, r2 = A.fit_gap(d, g, k=1.56)
+    assert abs(e0 - 0.46) < 1e-12 and abs(a - 4.64) < 1e-12 and k == 1.56 and r2 == pytest.approx(1.0)
