@@ -120,6 +120,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch brings its own HIP runtime, which the library then shares
+        # (same soname); initialise torch's device state first, so that a
+        # library call that touches the device before any tensor does (for
+        # example creating the density network) cannot leave torch unable
+        # to see the GPU
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
         L = C.CDLL(LIB_PATH)
         L.chf_last_error.restype = C.c_char_p
         L.chf_last_error.argtypes = []
