@@ -113,14 +113,16 @@ def predicted_start(net, H, cluster):
     return rho_sad, rho0
 
 
-def evaluate(net, clusters, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, log=print):
+def evaluate(net, clusters, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, log=print, first_iters: int = 4):
+    """SCF from the superposition start and from the learned start, same
+    schedule and start vectors; steps to SRE < sre_tol_ry and energies."""
     rows = []
     for c in clusters:
-        st = S.setup(c, pp, dtype=dtype)
+        st = S.setup(c, pp, dtype=dtype, first_iters=first_iters)
         rho_sad, rho0 = predicted_start(net, st["H"], c)
         log(f"eval Si{c.n_si}H{c.n_h}: from the superposition start")
         r_sad = S.run(st, rho_sad, max_steps=80, sre_tol_ry=sre_tol_ry, log=log)
-        st2 = S.setup(c, pp, dtype=dtype)
+        st2 = S.setup(c, pp, dtype=dtype, first_iters=first_iters)
         _, rho0b = predicted_start(net, st2["H"], c)
         log(f"eval Si{c.n_si}H{c.n_h}: from the learned start")
         r_net = S.run(st2, rho0b, max_steps=80, sre_tol_ry=sre_tol_ry, log=log)

@@ -24,12 +24,13 @@ class ScfResult:
 
 def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nvec: int | None = None,
           x_seed: int = 2001, lanczos_seed: int = 3001, margin: float = 6.0, mix_beta: float = 0.1,
-          mix_history: int = 8):
+          mix_history: int = 8, first_iters: int = 4):
     """Hamiltonian, context, SCF state and the start block for a cluster.
 
     Anderson mixing defaults to beta = 0.1 with 8 past densities: at
     beta = 0.3 the density of clusters from 3 nm up sloshes without
-    converging."""
+    converging.  ``first_iters`` ChFSI iterations run in the first SCF step
+    (the paper's schedule: 4, then 1 per step)."""
     import torch
     from synth.cluster import n_states
     radius = cluster.domain_radius(margin)
@@ -54,7 +55,7 @@ def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nve
     v0 = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
     v0[rows] = torch.from_numpy(np.random.default_rng(lanczos_seed).standard_normal(H.n_points)).cuda()
     eii = B.ion_energy(cluster.pos, cluster.species, pp)
-    prm = B.ScfParams(ne, M, degree, 4, 1, 10, code, code, mix_history, mix_beta, 1e-12, eii)
+    prm = B.ScfParams(ne, M, degree, first_iters, 1, 10, code, code, mix_history, mix_beta, 1e-12, eii)
     return dict(H=H, ctx=ctx, prm=prm, X=X, W=torch.zeros_like(X), v0=v0, rows=rows, ne=ne, M=M)
 
 
