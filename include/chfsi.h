@@ -334,6 +334,14 @@ int dnet_mse(dnet* net, const float* y_dev, const float* t_dev, int64_t n, doubl
  * cells outside the box read 0. */
 int dnet_crop(const float* box_dev, int D, int S, int ox, int oy, int oz, int sym, float* patch_dev, void* stream);
 
+/* out [D^3] = box - G_sigma * box: the box minus its blur by a separable
+ * Gaussian of width sigma (cells), truncated at ceil(3 sigma) and
+ * normalised, with zero values outside the box (x fastest).  Removes the
+ * long-wavelength part of a predicted density correction, where the
+ * network's errors concentrate.  work_dev: 2 D^3 floats of scratch; out may
+ * alias neither box nor work.  Synchronises the stream. */
+int dnet_highpass(const float* box_dev, int D, double sigma, float* out_dev, float* work_dev, void* stream);
+
 /* Grid rows <-> cubic box of edge D (x-fastest) holding grid point (i, j, k)
  * at (i + off, j + off, k + off): box = scale * rows (cells without a grid
  * point 0); rows_out = base_rows + box / scale on inside rows (padding 0). */

@@ -20,6 +20,8 @@ Layout: arrays are [C, D, H, W]; weights [C_out, C_in, 3, 3, 3] (or 1^3), bias [
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 LAYERS = [  # name, c_in multiple of C (None = 1 channel), c_out, kernel, stride
@@ -185,3 +187,17 @@ def adam_step(p: dict, g: dict, m: dict, v: dict, step: int, lr: float = 1e-3, b
         mh = m[k] / (1 - b1 ** step)
         vh = v[k] / (1 - b2 ** step)
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def gaussian_highpass(box: np.ndarray, sigma: float) -> np.ndarray:
+    """box - G_sigma * box for a cubic array: the separable Gaussian
+    exp(-k^2 / (2 sigma^2)) truncated at |k| <= ceil(3 sigma), normalised to
+    unit sum, applied along each axis in turn with zero values outside."""
+    r = int(math.ceil(3.0 * sigma))
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-k * k / (2.0 * sigma * sigma))
+    g /= g.sum()
+    out = np.asarray(box, dtype=np.float64)
+    for axis in range(3):
+        out = np.apply_along_axis(lambda v: np.convolve(v, g, mode="same"), axis, out)
+    return np.asarray(box, dtype=np.float64) - out

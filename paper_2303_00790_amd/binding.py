@@ -107,6 +107,7 @@ _SIGS = {
     "dnet_adam": [P, C.c_float, INT, P],
     "dnet_mse": [P, P, P, I64, C.POINTER(D), P, P],
     "dnet_crop": [P, INT, INT, INT, INT, INT, INT, P, P],
+    "dnet_highpass": [P, INT, D, P, P, P],
     "chf_rows_to_box": [P, P, D, P, INT, INT, P],
     "chf_box_to_rows": [P, P, INT, INT, D, P, P, P],
 }
@@ -465,6 +466,10 @@ def dnet_plan(S: int) -> list[int]:
 
 def crop(box, D: int, S: int, origin, sym: int, patch) -> None:
     call("dnet_crop", _ptr(box), D, S, int(origin[0]), int(origin[1]), int(origin[2]), sym, _ptr(patch), _stream())
+
+
+def highpass(box, D: int, sigma: float, out, work) -> None:
+    call("dnet_highpass", _ptr(box), D, float(sigma), _ptr(out), _ptr(work), _stream())
 
 
 def rows_to_box(H: "Hamiltonian", rows, scale: float, box, D: int, off: int) -> None:

@@ -390,6 +390,29 @@ __global__ void box_to_rows_kernel(int64_t n_rows, const int32_t* __restrict__ i
     out[r] = v;
 }
 
+// one pass of a separable, truncated, normalised Gaussian along one axis of
+// a cubic box (x fastest), zero outside: out[i] = sum_k g[k + r] in[i + k e]
+__global__ void blur_pass_kernel(int D, int axis, int r, const float* __restrict__ g, const float* __restrict__ in,
+                                 float* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = int64_t(D) * D * D;
+    if (i >= n) return;
+    const int x = int(i % D), y = int((i / D) % D), z = int(i / (int64_t(D) * D));
+    const int c = axis == 0 ? x : (axis == 1 ? y : z);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? D : int64_t(D) * D);
+    float acc = 0.f;
+    for (int k = -r; k <= r; ++k) {
+        const int q = c + k;
+        if (q >= 0 && q < D) acc = fmaf(g[k + r], in[i + k * stride], acc);
+    }
+    out[i] = acc;
+}
+
+__global__ void sub_kernel(int64_t n, const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
 static uint64_t splitmix(uint64_t& s) {
     uint64_t z = (s += 0x9e3779b97f4a7c15ull);
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -820,6 +843,29 @@ int chf_box_to_rows(chf_ham* H, const float* box, int D, int off, double scale, 
         box_to_rows_kernel<<<nb(H->grid.n_rows), 256, 0, static_cast<hipStream_t>(stream)>>>(
             H->grid.n_rows, H->row_ijk4.as<int32_t>(), box, D, off, 1.0 / scale, base, out);
         LAUNCH_CHECK();
+    });
+}
+
+int dnet_highpass(const float* box, int D, double sigma, float* out, float* work, void* stream) {
+    return dguard([&] {
+        if (!box || !out || !work || D < 1 || !(sigma > 0) || sigma > 64) fail(CHF_EINVAL, "dnet_highpass: bad argument");
+        const int r = int(std::ceil(3.0 * sigma));
+        std::vector<float> g(size_t(2 * r + 1));
+        double tot = 0;
+        for (int k = -r; k <= r; ++k) tot += std::exp(-double(k) * k / (2.0 * sigma * sigma));
+        for (int k = -r; k <= r; ++k) g[size_t(k + r)] = float(std::exp(-double(k) * k / (2.0 * sigma * sigma)) / tot);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf gd;
+        upload(gd, g, s);
+        const int64_t n = int64_t(D) * D * D;
+        float* t1 = work;
+        float* t2 = work + n;
+        blur_pass_kernel<<<nb(n), 256, 0, s>>>(D, 0, r, gd.as<float>(), box, t1);
+        blur_pass_kernel<<<nb(n), 256, 0, s>>>(D, 1, r, gd.as<float>(), t1, t2);
+        blur_pass_kernel<<<nb(n), 256, 0, s>>>(D, 2, r, gd.as<float>(), t2, t1);
+        sub_kernel<<<nb(n), 256, 0, s>>>(n, box, t1, out);
+        LAUNCH_CHECK();
+        HIP_CHECK(hipStreamSynchronize(s));   // the weights buffer is freed on return
     });
 }
 

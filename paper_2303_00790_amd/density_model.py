@@ -98,8 +98,13 @@ def train(net, data, steps: int, patch: int = 64, lr: float = 1e-3, seed: int = 
     return losses
 
 
-def predicted_start(net, H, cluster):
-    """rho_0 = renormalise(max(rho_sad + net(rho_sad), 0)) on the full box."""
+def predicted_start(net, H, cluster, highpass_sigma: float = 0.0):
+    """rho_0 = renormalise(max(rho_sad + net(rho_sad), 0)) on the full box.
+
+    With highpass_sigma > 0 (cells) only the part of the predicted correction
+    above the Gaussian's wavelengths is kept: the network reproduces the
+    bond-scale correction but misses its long-wavelength charge shifts, which
+    the Hartree potential amplifies."""
     import torch
     rho_sad = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
     D, off = box_geometry(H)
@@ -107,23 +112,30 @@ def predicted_start(net, H, cluster):
     B.rows_to_box(H, rho_sad, SCALE, box, D, off)
     out = torch.zeros_like(box)
     net.forward(box, out)
+    if highpass_sigma > 0:
+        work = torch.zeros(2 * D ** 3, dtype=torch.float32, device="cuda")
+        hp = torch.zeros_like(box)
+        B.highpass(out, D, highpass_sigma, hp, work)
+        out = hp
+        del work
     rho0 = torch.zeros_like(rho_sad)
     B.box_to_rows(H, out, D, off, SCALE, rho_sad, rho0)
     H.density_fix(rho0, cluster.n_electrons)
     return rho_sad, rho0
 
 
-def evaluate(net, clusters, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, log=print, first_iters: int = 4):
+def evaluate(net, clusters, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, log=print, first_iters: int = 4,
+             highpass_sigma: float = 0.0):
     """SCF from the superposition start and from the learned start, same
     schedule and start vectors; steps to SRE < sre_tol_ry and energies."""
     rows = []
     for c in clusters:
         st = S.setup(c, pp, dtype=dtype, first_iters=first_iters)
-        rho_sad, rho0 = predicted_start(net, st["H"], c)
+        rho_sad, rho0 = predicted_start(net, st["H"], c, highpass_sigma)
         log(f"eval Si{c.n_si}H{c.n_h}: from the superposition start")
         r_sad = S.run(st, rho_sad, max_steps=80, sre_tol_ry=sre_tol_ry, log=log)
         st2 = S.setup(c, pp, dtype=dtype, first_iters=first_iters)
-        _, rho0b = predicted_start(net, st2["H"], c)
+        _, rho0b = predicted_start(net, st2["H"], c, highpass_sigma)
         log(f"eval Si{c.n_si}H{c.n_h}: from the learned start")
         r_net = S.run(st2, rho0b, max_steps=80, sre_tol_ry=sre_tol_ry, log=log)
         row = dict(n_atoms=c.n_atoms, steps_sad=r_sad.steps, steps_net=r_net.steps, conv_sad=r_sad.converged,

@@ -41,6 +41,8 @@ def main(argv=None):
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--eval-seed", type=int, default=20000)
     ap.add_argument("--first-iters", type=int, default=4, help="ChFSI iterations in the first SCF step of the evaluation")
+    ap.add_argument("--highpass", type=float, default=0.0,
+                    help="keep only the correction above this Gaussian width (grid cells); 0 keeps all of it")
     ap.add_argument("--out", default=None)
     ap.add_argument("--params-out", default=None)
     ap.add_argument("--params-in", default=None, help="skip data and training; evaluate these weights")
@@ -69,9 +71,10 @@ def main(argv=None):
         del data
     if args.eval > 0:
         evals = [make_cluster(5.0 * args.eval_diam, args.eval_seed + i, sigma_angstrom=0.02) for i in range(args.eval)]
-        rows = DM.evaluate(net, evals, MODEL_PP, dtype=args.dtype, log=log, first_iters=args.first_iters)
+        rows = DM.evaluate(net, evals, MODEL_PP, dtype=args.dtype, log=log, first_iters=args.first_iters,
+                           highpass_sigma=args.highpass)
         res.update({"eval_diam_nm": args.eval_diam, "eval_seeds": [args.eval_seed + i for i in range(args.eval)],
-                    "first_iters": args.first_iters,
+                    "first_iters": args.first_iters, "highpass_sigma": args.highpass,
                     "eval": rows, "mean_steps_sad": float(np.mean([r["steps_sad"] for r in rows])),
                     "mean_steps_net": float(np.mean([r["steps_net"] for r in rows])),
                     "max_de_per_atom": float(max(r["de_per_atom"] for r in rows))})

@@ -1,6 +1,8 @@
 """Pins of the density-network oracle: convolution against a brute-force
 loop, every backward pass against central finite differences, the upsampling
 adjoint identity, and Adam's closed-form first step."""
+import math
+
 import numpy as np
 import pytest
 
@@ -107,3 +109,25 @@ def test_untrained_network_predicts_zero():
     p = U.init_params(C=4, seed=1)
     y = U.forward(p, np.random.default_rng(0).standard_normal((1, 8, 8, 8)))
     assert np.all(y == 0.0)
+
+
+def test_gaussian_highpass_closed_forms():
+    # a unit impulse away from the faces: the blur is the separable product
+    # of the normalised weights, so the high-pass is 1 - g0^3 at the impulse
+    # and -g_i g_j g_k elsewhere; a constant field far from the faces is
+    # removed exactly
+    sigma = 1.3
+    r = math.ceil(3 * sigma)
+    k = np.arange(-r, r + 1)
+    g = np.exp(-k * k / (2 * sigma * sigma))
+    g /= g.sum()
+    D = 2 * r + 5
+    c = D // 2
+    b = np.zeros((D, D, D))
+    b[c, c, c] = 1.0
+    hp = U.gaussian_highpass(b, sigma)
+    assert abs(hp[c, c, c] - (1.0 - g[r] ** 3)) < 1e-14
+    assert abs(hp[c + 1, c - 2, c + 3] + g[r + 1] * g[r - 2] * g[r + 3]) < 1e-15
+    assert abs(hp.sum()) < 1e-13
+    ones = U.gaussian_highpass(np.ones((D, D, D)), sigma)
+    assert np.abs(ones[r:D - r, r:D - r, r:D - r]).max() < 1e-14
