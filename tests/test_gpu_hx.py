@@ -199,3 +199,26 @@ def test_no_projector_atoms(species):
         Yg = torch.full_like(Xg, float("nan"))
         Hg.apply(Xg, Yg, generic=generic)
         assert relerr(Yg[rows].cpu().numpy(), ref) < 1e-12
+
+
+def test_more_atoms_per_block_than_staged():
+    # more than 64 projector atoms touching one 8^3 block: the tiled kernel
+    # reads the KB coefficients from global memory instead of staging them
+    from paper_2303_00790_amd import binding as B
+    rng = np.random.default_rng(31)
+    pos = rng.uniform(-3.0, 3.0, size=(90, 3))
+    spc = np.zeros(90, np.int32)
+    pp = OH.PseudoParams(h_s=2.0, h_p=0.5)
+    radius = 9.0
+    g = G.build_grid(radius, H_SPACING)
+    Ho = OH.build_hamiltonian(g, pos, spc, pp)
+    Hg = B.Hamiltonian(pos, spc, pp, H_SPACING, radius, B.ORDER_HILBERT, keep_nbr=True)
+    rows = torch.from_numpy(g.row_of_rank).cuda()
+    X = random_block(g.n, 8, 2500)
+    Xg = torch.zeros((Hg.n_rows, 8), dtype=torch.float64, device="cuda")
+    Xg[rows] = torch.from_numpy(X).cuda()
+    ref = Ho.apply(X)
+    for generic in (False, True):
+        Yg = torch.full_like(Xg, float("nan"))
+        Hg.apply(Xg, Yg, generic=generic)
+        assert relerr(Yg[rows].cpu().numpy(), ref) < 1e-12
