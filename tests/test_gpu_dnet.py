@@ -144,3 +144,52 @@ def test_highpass_matches_oracle():
     B.highpass(bg, D, sigma, out, work)
     got = out.cpu().numpy().reshape(D, D, D)   # z, y, x with x fastest: the oracle array's axes in the same order
     assert np.abs(got - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+@pytest.fixture(scope="module")
+def grid_system():
+    from gpu_system import build
+    return build()
+
+
+def test_rows_box_round_trip(grid_system):
+    # rows -> box places grid point (i, j, k) at cell (i, j, k) + off of a
+    # D^3 box, x fastest, scaled; box -> rows reads it back (FP32 box)
+    from paper_2303_00790_amd import binding as B
+    from paper_2303_00790_amd import density_model as DM
+    s = grid_system
+    H = s["Hg"]
+    D, off = DM.box_geometry(H)
+    rng = np.random.default_rng(5)
+    vals = rng.uniform(0.0, 0.05, s["g"].n)
+    rows = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
+    rows[s["rows"]] = torch.from_numpy(vals).cuda()
+    box = torch.full((D ** 3,), float("nan"), dtype=torch.float32, device="cuda")
+    B.rows_to_box(H, rows, 30.0, box, D, off)
+    b = box.cpu().numpy().reshape(D, D, D)
+    ijk = s["g"].ijk + off
+    assert np.allclose(b[ijk[:, 2], ijk[:, 1], ijk[:, 0]], (30.0 * vals).astype(np.float32), rtol=0, atol=0)
+    assert np.count_nonzero(b) == np.count_nonzero(vals)
+    back = torch.full_like(rows, float("nan"))
+    B.box_to_rows(H, box, D, off, 30.0, None, back)
+    got = back.cpu().numpy()
+    assert np.abs(got[s["g"].row_of_rank] - vals).max() < 1e-7 * vals.max()
+    pad = np.ones(H.n_rows, bool)
+    pad[s["g"].row_of_rank] = False
+    assert not got[pad].any()
+
+
+def test_density_fix_clamps_and_renormalises(grid_system):
+    # rho <- max(rho, 0) * N_e / (h^3 sum max(rho, 0)) on the inside rows
+    s = grid_system
+    H = s["Hg"]
+    rng = np.random.default_rng(6)
+    vals = rng.normal(0.01, 0.02, s["g"].n)
+    rows = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
+    rows[s["rows"]] = torch.from_numpy(vals).cuda()
+    ne = 176
+    H.density_fix(rows, ne)
+    ref = np.maximum(vals, 0.0)
+    ref *= ne / (0.7 ** 3 * ref.sum())
+    got = rows.cpu().numpy()[s["g"].row_of_rank]
+    assert np.abs(got - ref).max() < 1e-13 * ref.max()
