@@ -291,6 +291,19 @@ int scf_step(chf_scf* scf, void* X_dev, int64_t ldx, void* work_dev, int64_t ldw
  * state (device to device, on the SCF's stream). */
 int chf_scf_get_fields(chf_scf* scf, double* rho_in_dev, double* vh_dev);
 
+/* Checkpoint / resume of the SCF state kept by the handle (the paper's runs
+ * last days; a resumed run continues where the saved one stopped): step
+ * counter, filter bounds, rho_in, V_H and the Anderson history.  The caller
+ * owns X and saves it alongside.  chf_scf_state_size gives the length in
+ * doubles (it grows with the history, up to 8 + (2 + 2 mix_history) n_rows);
+ * chf_scf_save copies the state into state_host and synchronises;
+ * chf_scf_load restores a state saved from an SCF of the same grid and
+ * mixing history (CHF_EINVAL on a version, grid, history or size mismatch).
+ * Resuming and stepping reproduces the uninterrupted run bit for bit. */
+int chf_scf_state_size(const chf_scf* scf, int64_t* n_doubles);
+int chf_scf_save(chf_scf* scf, double* state_host);
+int chf_scf_load(chf_scf* scf, const double* state_host, int64_t n_doubles);
+
 /* ---------------------------------------------------------------------------
  * Learned initial density: a 3-D U-Net (4 levels, `channels` channels, two
  * 3^3 conv + SiLU per level, stride-2 conv down, nearest upsample + 3^3 conv

@@ -94,6 +94,9 @@ _SIGS = {
     "chf_scf_destroy": [P],
     "scf_step": [P, P, I64, P, I64, C.POINTER(ScfReport), P],
     "chf_scf_get_fields": [P, P, P],
+    "chf_scf_state_size": [P, P],
+    "chf_scf_save": [P, P],
+    "chf_scf_load": [P, P, I64],
     "dnet_create": [INT, C.c_uint64, C.POINTER(P)],
     "dnet_destroy": [P],
     "dnet_param_count": [P, C.POINTER(I64)],
@@ -380,6 +383,18 @@ class Scf:
         eig = np.zeros(self.nvec, np.float64)
         call("scf_step", self.handle, px, ldx, pw, ldw, C.byref(rep), P(eig.ctypes.data))
         return rep, eig
+
+    def save(self) -> np.ndarray:
+        """Checkpoint of the SCF state (host array; X is saved by the caller)."""
+        n = I64()
+        call("chf_scf_state_size", self.handle, C.byref(n))
+        out = np.zeros(n.value, np.float64)
+        call("chf_scf_save", self.handle, P(out.ctypes.data))
+        return out
+
+    def load(self, state: np.ndarray) -> None:
+        state = np.ascontiguousarray(state, dtype=np.float64)
+        call("chf_scf_load", self.handle, P(state.ctypes.data), int(state.size))
 
     def fields(self, rho_in, vh=None):
         call("chf_scf_get_fields", self.handle, _ptr(rho_in) if rho_in is not None else None,

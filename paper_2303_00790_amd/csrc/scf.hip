@@ -908,4 +908,67 @@ int chf_scf_get_fields(chf_scf* S, double* rho_in, double* vh) {
     });
 }
 
+// Checkpoint layout (doubles): a header of kCkptHeader values {version,
+// step, have_bounds, a, a0, n_hist, n_rows, mix_history}, then rho_in,
+// V_H, the n_hist past densities and the n_hist past residuals ([n_rows]
+// each, oldest first).
+static constexpr int64_t kCkptHeader = 8;
+static constexpr double kCkptVersion = 1.0;
+
+int chf_scf_state_size(const chf_scf* S, int64_t* n_doubles) {
+    return scf_guard([&] {
+        if (!S || !n_doubles) fail(CHF_EINVAL, "chf_scf_state_size: null argument");
+        *n_doubles = kCkptHeader + int64_t(2 + 2 * S->n_hist) * S->n;
+    });
+}
+
+int chf_scf_save(chf_scf* S, double* state_host) {
+    return scf_guard([&] {
+        if (!S || !state_host) fail(CHF_EINVAL, "chf_scf_save: null argument");
+        hipStream_t s = S->H->stream;
+        const double hdr[kCkptHeader] = {kCkptVersion, double(S->step), S->have_bounds ? 1.0 : 0.0, S->a, S->a0,
+                                         double(S->n_hist), double(S->n), double(S->prm.mix_history)};
+        std::memcpy(state_host, hdr, sizeof(hdr));
+        const size_t nb = size_t(S->n) * sizeof(double);
+        double* out = state_host + kCkptHeader;
+        HIP_CHECK(hipMemcpyAsync(out, S->f(F_RHO), nb, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(out + S->n, S->f(F_VH), nb, hipMemcpyDeviceToHost, s));
+        for (int j = 0; j < S->n_hist; ++j) {
+            HIP_CHECK(hipMemcpyAsync(out + (2 + j) * S->n, S->hx(j), nb, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(out + (2 + S->n_hist + j) * S->n, S->hf(j), nb, hipMemcpyDeviceToHost, s));
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+    });
+}
+
+int chf_scf_load(chf_scf* S, const double* state_host, int64_t n_doubles) {
+    return scf_guard([&] {
+        if (!S || !state_host) fail(CHF_EINVAL, "chf_scf_load: null argument");
+        if (n_doubles < kCkptHeader) fail(CHF_EINVAL, "chf_scf_load: state too short");
+        const double* h = state_host;
+        if (h[0] != kCkptVersion) fail(CHF_EINVAL, "chf_scf_load: unknown state version");
+        if (int64_t(h[6]) != S->n || int(h[7]) != S->prm.mix_history)
+            fail(CHF_EINVAL, "chf_scf_load: state from a different grid or mixing history");
+        const int n_hist = int(h[5]);
+        if (n_hist < 0 || n_hist > S->prm.mix_history || !(h[1] >= 0))
+            fail(CHF_EINVAL, "chf_scf_load: corrupt state header");
+        if (n_doubles != kCkptHeader + int64_t(2 + 2 * n_hist) * S->n) fail(CHF_EINVAL, "chf_scf_load: state size mismatch");
+        hipStream_t s = S->H->stream;
+        const size_t nb = size_t(S->n) * sizeof(double);
+        const double* in = state_host + kCkptHeader;
+        HIP_CHECK(hipMemcpyAsync(S->f(F_RHO), in, nb, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(S->f(F_VH), in + S->n, nb, hipMemcpyHostToDevice, s));
+        for (int j = 0; j < n_hist; ++j) {
+            HIP_CHECK(hipMemcpyAsync(S->hx(j), in + (2 + j) * S->n, nb, hipMemcpyHostToDevice, s));
+            HIP_CHECK(hipMemcpyAsync(S->hf(j), in + (2 + n_hist + j) * S->n, nb, hipMemcpyHostToDevice, s));
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        S->step = int(h[1]);
+        S->have_bounds = h[2] != 0.0;
+        S->a = h[3];
+        S->a0 = h[4];
+        S->n_hist = n_hist;
+    });
+}
+
 }  // extern "C"

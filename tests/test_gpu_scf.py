@@ -114,3 +114,48 @@ def test_scf_steps_fp64(si35):
     vh = torch.zeros_like(rho_in)
     scf.fields(rho_in, vh)
     assert relerr(from_rows(s, rho_in), st.rho_in) < 1e-8
+
+
+def test_checkpoint_resume_is_bit_exact(si35):
+    """Saving the SCF state after three steps and resuming it in a fresh
+    handle reproduces the fourth step of the uninterrupted run exactly."""
+    s = si35
+    B = s["B"]
+    c = s["c"]
+    ne = c.n_electrons
+    M = n_states(ne)
+    X0 = random_block(s["g"].n, M, 2002)
+    v0 = to_rows(s, random_block(s["g"].n, 1, 3002)[:, 0], torch.float64)
+    eii = OS.ion_energy(c.pos, s["pp"].charges(c.species))
+    prm = B.ScfParams(ne, M, 10, 4, 1, 10, B.CHF_F64, B.CHF_F64, 6, 0.3, 1e-12, eii)
+    rho0 = s["Hg"].sad_density(c.pos, c.species, ne)
+    scf = B.Scf(s["Hg"], s["ctx"], prm, rho0, v0)
+    X = to_rows(s, X0, torch.float64)
+    W = torch.zeros_like(X)
+    for _ in range(3):
+        scf.step(X, W)
+    state = scf.save()
+    assert state.size == 8 + (2 + 2 * 3) * s["Hg"].n_rows
+    X_saved = X.clone()
+    rep, eig = scf.step(X, W)
+    rho_a = torch.zeros(s["Hg"].n_rows, dtype=torch.float64, device="cuda")
+    scf.fields(rho_a)
+
+    fresh = B.Scf(s["Hg"], s["ctx"], prm, rho0, v0)
+    fresh.load(state)
+    X2 = X_saved.clone()
+    rep2, eig2 = fresh.step(X2, W)
+    rho_b = torch.zeros_like(rho_a)
+    fresh.fields(rho_b)
+    assert rep2.step == rep.step == 4
+    assert rep2.energy == rep.energy and rep2.sre_ry == rep.sre_ry
+    assert np.array_equal(eig, eig2)
+    assert torch.equal(X, X2) and torch.equal(rho_a, rho_b)
+
+    # a state from another mixing history or a truncated buffer is refused
+    other = B.Scf(s["Hg"], s["ctx"], B.ScfParams(ne, M, 10, 4, 1, 10, B.CHF_F64, B.CHF_F64, 5, 0.3, 1e-12, eii),
+                  rho0, v0)
+    with pytest.raises(B.ChfError):
+        other.load(state)
+    with pytest.raises(B.ChfError):
+        fresh.load(state[:-1])
