@@ -47,6 +47,14 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 of the H X kernel source (the counters in profiles/ name it)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2303_00790_amd", "csrc", "hx.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def cpu_baseline(degree: int, sample: str = "auto", workload: str = "d16nm") -> dict:
     """The FP64 oracle filter timed on the host on a bounded sample: by
     default the 0.55 nm cluster's full grid (72,455 points) with 1024 vectors;
@@ -159,10 +167,12 @@ def main():
     hx_avg_s = tm["hx_ms"] / 1e3 / max(1, launches)
     achieved = alg_bytes_per_launch / hx_avg_s / 1e9
     kernel = ("hx_generic_kernel" if generic else "hx_tiled_kernel")
+    # HBM traffic from the committed counter runs, only if they were taken on
+    # the kernel source as it is now
     traffic = None
     if not generic and os.path.exists(args.traffic):
         rec = json.load(open(args.traffic)).get(f"{wl.name}:{dtype_name}:{nvec}")
-        if rec:
+        if rec and rec.get("source_sha256") == kernel_source_hash():
             traffic = rec.get("bytes_per_launch")
     out = {
         "metric": "filtered gridpt*vectors/s (Chebyshev filter, one GPU)",

@@ -103,6 +103,10 @@ template <class T>
 struct StepCoef {
     T c[7];        // -1/2 c_k / h^2 (c[0] already multiplied by 3: three axes)
     T alpha, shift, beta;
+    // the same step with alpha folded in (tiled kernel):
+    //   y = sum_k ac[k] (X(p+k) + X(p-k)) + (d0 + alpha V(p)) X(p) + alpha KB - beta Z
+    T ac[7];       // alpha c[k], k >= 1 (ac[0] unused)
+    T d0;          // alpha (c[0] - shift)
 };
 
 template <class T>
@@ -173,6 +177,9 @@ StepCoef<T> make_coef(const chf_ham* H, double alpha, double shift, double beta)
     k.alpha = T(alpha);
     k.shift = T(shift);
     k.beta = T(beta);
+    k.ac[0] = T(0);
+    for (int i = 1; i < 7; ++i) k.ac[i] = T(alpha * H->coef[i]);
+    k.d0 = T(alpha * (3.0 * H->coef[0] - shift));
     return k;
 }
 
@@ -199,22 +206,18 @@ void launch_hx_generic(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, c
 }
 
 // ---------------------------------------------------------------------------
-// Hilbert-blocked tiled H X
+// Hilbert-blocked tiled H X (hx_tiled_kernel below)
 //
-// Workgroup: 512 threads = 64 columns (x, y) of one 8^3 block x 8 "quads"
-// of 16 bytes (4 floats or 2 doubles) -> a 128-byte vector chunk per row
-// (32 FP32 or 16 FP64 vectors).  Each thread keeps X(x, y, z-6 .. z+6) of
-// its column and quad in registers and marches z = 0..7; the x/y neighbours
-// of plane z (the plane plus its 6-deep halos from the -x/+x/-y/+y
-// neighbour blocks) are staged in LDS, double-buffered so that one barrier
-// per plane suffices.  The KB scatter reads the per-row entry lists and the
-// coefficients C of the step; the Chebyshev update is fused into the store.
+// One workgroup per tile = one 8^3 block x one 128-byte vector chunk (32 FP32
+// or 16 FP64 vectors): 1024 threads = 64 columns (x, y) x 16 lanes of 8
+// bytes.  Each thread keeps X(x, y, z-6 .. z+13) of its column and lane in
+// registers and marches z = 0..7; the x/y neighbours of plane z (the plane
+// plus its 6-deep halos from the -x/+x/-y/+y neighbour blocks) are staged in
+// LDS as a 20 x 20 square, double-buffered so that one barrier per plane
+// suffices.  The KB term of each row is applied in the march from the
+// block's staged coefficients; the Chebyshev update is fused into the store.
 // Rows outside the sphere are stored as zero; on input they must hold zero
 // (the layout contract), so they enter the stencil as the zero boundary.
-//
-// LDS plane layout (rows of 128 B): a 20 x 8 strip for x in [-6, 14) and
-// y in [0, 8) (160 rows) followed by two 8 x 6 strips for y in [-6, 0) and
-// [8, 14) (48 rows each): 256 rows = 32 KB per plane, 64 KB double-buffered.
 // ---------------------------------------------------------------------------
 template <class T>
 struct Quad;
@@ -363,13 +366,6 @@ void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipSt
     LAUNCH_CHECK();
 }
 
-__device__ inline int lds_row(int x, int y) {
-    // x in [-6, 14), y in [-6, 14), not both outside [0, 8)
-    if (y >= 0 && y < 8) return (x + 6) + 20 * y;
-    if (y < 0) return 160 + x + 8 * (y + 6);
-    return 208 + x + 8 * (y - 8);
-}
-
 // 8-byte lane values of the tiled kernel: two floats or one double
 template <class T>
 struct Lane;
@@ -408,10 +404,12 @@ __device__ inline void static_for(F&& f) {
     }
 }
 
-// value of lane K of this lane's 16-lane row (DPP row_newbcast)
+// value of lane K of this lane's 16-lane row (DPP row_newbcast).  All rows
+// and banks are written and the source lane is always valid, so no old value
+// is needed (mov_dpp leaves it undefined and saves a register clear).
 template <int K>
 __device__ inline int row_bcast(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x150 + K, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, false);
 }
 template <int K>
 __device__ inline float row_bcast(float v) {
@@ -473,7 +471,6 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
     constexpr int NT = 64 * LANES;       // threads
     constexpr int LSH = LANES == 16 ? 4 : 3;
     constexpr int CPW = 64 / LANES;      // columns per wave
-    constexpr int G = 16 / LANES;        // sibling chunks sharing a 128-byte line
     static_assert(LANES == 16 || LANES == 8, "LANES is 8 or 16");
     // LDS plane: the full 20 x 20 square x in [-6, 14), y in [-6, 14) (corners
     // unused) so every neighbour is a constant offset from the centre
@@ -481,11 +478,11 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
     __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][LANES][4];
 
     // XCD-aware tile order: workgroup ids are dealt round-robin to the 8
-    // XCDs; give each XCD a contiguous run of the tile sequence (chunk groups
-    // major, Hilbert-ordered blocks, the G sibling chunks of a block last) so
-    // that neighbouring blocks share its L2 and sibling chunks share lines.
-    const int n_groups = (n_chunks + G - 1) / G;
-    const int64_t ntiles = n_blocks * n_groups * G;
+    // XCDs; give each XCD a contiguous run of the tile sequence (blocks in
+    // Hilbert order, the vector chunks of a block adjacent) so that
+    // neighbouring blocks share its L2 and the chunks of a block share the
+    // block's tables (KB entries, V_eff, masks).
+    const int64_t ntiles = n_blocks * n_chunks;
     const int64_t per_xcd = (ntiles + 7) / 8;
     const int64_t tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (tile >= ntiles) return;
@@ -516,13 +513,8 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
         unsigned hoff[3];
     };
     TileIO io;
-    {
-        const int64_t per_group = n_blocks * G;
-        const int grp = int(tile / per_group);
-        const int64_t rem = tile - grp * per_group;
-        io.blk = rem / G;
-        io.chunk = grp * G + int(rem - io.blk * G);
-    }
+    io.blk = tile / n_chunks;
+    io.chunk = int(tile - io.blk * n_chunks);
 #pragma unroll
     for (int f = 0; f < 6; ++f) io.nbs[f] = bnb[6 * io.blk + f];
     {
@@ -607,8 +599,8 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                 const int e = t + NT * u;         // (atom slot, lm, lane)
                 const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
                 const int vb = io.chunk * CH + lp * LN;
-                if (sl < na && vb < nvec)
-                    cstage[u] = *reinterpret_cast<const V*>(C + (int64_t(blk_atoms[a0 + sl]) * 4 + lm) * nvec + vb);
+                if (sl < na && vb < nvec)         // staged with alpha applied
+                    cstage[u] = lscale(k.alpha, *reinterpret_cast<const V*>(C + (int64_t(blk_atoms[a0 + sl]) * 4 + lm) * nvec + vb));
                 else
                     cstage[u] = lz<V>();
             }
@@ -682,7 +674,9 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             }
 
             const int l = lrow + 64 * z;
-            V acc = lscale(k.c[0], w[z + 6]);
+            // alpha-scaled off-diagonal stencil first; the diagonal, which
+            // needs V_eff(p) from memory, is added last
+            V acc;
 #pragma unroll
             for (int s = 1; s <= 6; ++s) {
                 V sum = ladd(w[z + 6 - s], w[z + 6 + s]);
@@ -690,10 +684,9 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                 sum = ladd(sum, plane[b][ctr + s][p]);
                 sum = ladd(sum, plane[b][ctr - 20 * s][p]);
                 sum = ladd(sum, plane[b][ctr + 20 * s][p]);
-                acc = lfma(k.c[s], sum, acc);
+                acc = s == 1 ? lscale(k.ac[1], sum) : lfma(k.ac[s], sum, acc);
             }
             const V xc = w[z + 6];
-            if (vr) acc = lfma(vr[l], xc, acc);
             if (INMARCH && kb) {
                 // KB term of row z: sum over its entries of h_l beta_lm C_lm
                 const int cnt = e_hi[z] - e_lo[z];
@@ -713,7 +706,8 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                     for (int m = 0; m < 4; ++m) acc = lfma(bb[m], cs[m], acc);
                 }
             }
-            V y = lscale(k.alpha, lfma(-k.shift, xc, acc));
+            const T dg = vr ? T(fma(k.alpha, vr[l], k.d0)) : k.d0;
+            V y = lfma(dg, xc, acc);
             if (Z) y = lfma(-k.beta, zcur, y);
             if (KEEP_R) {
                 r[z] = y;
@@ -787,9 +781,8 @@ static void launch_hx_tiled_l(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t
                               int nvec, const T* C, double alpha, double shift, double beta, hipStream_t s,
                               bool lap_only) {
     constexpr int CH = LANES * Lane<T>::N;
-    constexpr int G = 16 / LANES;
     const int n_chunks = (nvec + CH - 1) / CH;
-    const int64_t nt = H->grid.n_blocks * int64_t((n_chunks + G - 1) / G) * G;
+    const int64_t nt = H->grid.n_blocks * int64_t(n_chunks);
     const dim3 grid(unsigned(((nt + 7) / 8) * 8)), block(64 * LANES);
     const bool kb = !lap_only && H->proj.n_proj > 0;
     const bool stage = kb && H->proj.max_block_atoms <= kMaxBlockAtoms;
