@@ -40,6 +40,9 @@ def parse():
                     help="oracle sample: 'auto' (0.55 nm grid x 1024 vectors) or 'workload:K' (this workload's "
                          "grid x K vectors)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gram", type=int, default=0, metavar="M",
+                    help="instead of the filter, time the Gram product X^T X of an M-column block over the "
+                         "workload's rows (Cholesky-QR / Rayleigh-Ritz contraction) against the MFMA peak")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 4 GiB device copy (reference dispatch for HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -85,6 +88,43 @@ def cpu_baseline(degree: int, sample: str = "auto", workload: str = "d16nm") -> 
     return {"value": g.n * nvec / dt, "unit": "gridpt*vectors/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle degree-{degree} filter, {wl.name} grid ({g.n} points) x {nvec} vectors "
                       f"(scipy CSR SpMM, single-threaded), {dt:.1f} s"}
+
+
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix peaks
+
+
+def gram_bench(args, B, ctx, H, wl, dtype_name, tdtype, inside):
+    """Time S = X^T X for an M-column block over all rows of the workload grid
+    (the Gram product of Cholesky-QR and Rayleigh-Ritz): one JSON line with
+    TFLOP/s counted as 2 N M^2 (the plain product; the library computes all of
+    it) against the MFMA peak of the block dtype."""
+    import torch
+    m = args.gram
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl.x_seed)
+    X = torch.randn((H.n_rows, m), generator=gen, dtype=tdtype, device="cuda")
+    X.mul_(inside[:, None])
+    S = torch.empty((m, m), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        B.gram(ctx, X, X, S)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        B.gram(ctx, X, X, S)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    flops = 2.0 * H.n_rows * m * m
+    tf = flops / (ms / 1e3) / 1e12
+    print(json.dumps({
+        "metric": "Gram product X^T X TFLOP/s (2 N M^2 counted)", "value": tf, "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "dtype": dtype_name, "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.description}", "rows": H.n_rows, "columns": m},
+        "roofline": {"bound": "mfma", "achieved": tf, "peak": MFMA_PEAK_TFLOPS[dtype_name], "unit": "TFLOP/s",
+                     "frac": tf / MFMA_PEAK_TFLOPS[dtype_name], "traffic": None}}), flush=True)
 
 
 def main():
@@ -135,6 +175,9 @@ def main():
     print(f"# setup {t_setup:.1f} s: {H.n_points} points, {H.n_rows} rows, {H.n_blocks} blocks, "
           f"{H.n_proj} projector atoms, {H.n_pairs} pairs; bounds a0={a0:.4f} a={a:.4f} b={b:.4f}",
           file=sys.stderr, flush=True)
+    if args.gram:
+        gram_bench(args, B, ctx, H, wl, dtype_name, tdtype, inside)
+        return
 
     for _ in range(args.warmup):
         H.filter(X, W, wl.degree, a, b, a0, generic=generic)

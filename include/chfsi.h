@@ -193,17 +193,21 @@ int lanczos_bound(chf_ham* ham, chf_ctx* ctx, const double* v0_dev, int k, doubl
                   void* stream);
 
 /* S = A^T B for row-major blocks A [n_rows][lda] (m columns) and B [n_rows][ldb]
- * (n columns), accumulated on MFMA in the block precision; partial sums over
- * row slices are added in FP64.  S_dev is FP64 row-major [m][lds].  With
- * A == B and m == n only the upper triangle is computed and mirrored. */
+ * (n columns): products of row slices (at least 4096 rows each) accumulated on
+ * MFMA in the block precision (rocBLAS), the slice partials added in FP64 in
+ * slice order.  S_dev is FP64 row-major [m][lds].  With A == B and m == n the
+ * upper triangle is summed and mirrored, so S is exactly symmetric. */
 int gram(chf_ctx* ctx, chf_dtype dtype, const void* A_dev, int64_t lda, const void* B_dev,
          int64_t ldb, int64_t n_rows, int m, int n, double* S_dev, int64_t lds, void* stream);
 
 /* Cholesky-QR (paper: the subspace orthonormalisation of ChFSI):
  * S = X^T X (gram), S = R^T R in FP64, X <- X R^{-1} (the update in the block
- * precision).  On breakdown in FP32 the Gram is recomputed with the
- * vectors scaled by 1/norm and retried once (counted in *fallbacks, may be
- * NULL); CHF_ENOTPD if that fails too. */
+ * precision).  Breakdown: the factorisation fails, or (FP64 blocks) a pivot
+ * R_ii^2 falls below 1e-13 of column i's squared norm (the column is
+ * numerically dependent on the ones before it).  On breakdown a shifted
+ * Cholesky-QR (shift 1e-14 (FP64) / 1e-6 (FP32) of the mean diagonal) is
+ * followed by a plain pass (counted in *fallbacks, may be NULL); CHF_ENOTPD
+ * if that fails too. */
 int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int64_t n_rows, int nvec,
                    int* fallbacks, void* stream);
 

@@ -1,12 +1,13 @@
 // Dense and BLAS-1 pieces of ChFSI on gfx950: deterministic reductions, the
-// Lanczos upper bound, MFMA Gram products, Cholesky-QR and Rayleigh-Ritz.
+// Lanczos upper bound, Gram products, Cholesky-QR and Rayleigh-Ritz.
 //
 // Paper: ChFSI orthonormalises the filtered block and projects H onto it
 // (the CheFSI paragraph; details of the PARSEC implementation are deferred to
-// its ChFSI reference).  The Gram products X^T X and X^T (H X) are the dense
-// contractions of the method and run on MFMA; the M x M Cholesky factorisation
-// and symmetric eigensolve run in FP64 through rocSOLVER; the N x M x M block
-// updates X R^{-1} and X Q are plain GEMMs (rocBLAS).
+// its ChFSI reference).  The Gram products X^T X and X^T (H X) and the
+// N x M x M block updates X R^{-1} and X Q are plain GEMMs (rocBLAS on MFMA;
+// the Gram in row slices whose partials are summed in FP64); the M x M
+// Cholesky factorisation and symmetric eigensolve run in FP64 through
+// rocSOLVER.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -125,176 +126,78 @@ static double tridiag_eig(const std::vector<double>& d, const std::vector<double
 
 
 // ---------------------------------------------------------------------------
-// Gram products S = A^T B on MFMA
-//
-// Workgroup: 256 threads = 4 waves (2 x 2), output tile 64 x 64, each wave a
-// 32 x 32 sub-tile = 2 x 2 blocks of the 16 x 16 x 4 MFMA.  The reduction
-// runs over grid rows: every workgroup owns one row slice (split-K); A and B
-// panels of 16 rows are staged in LDS (double-buffered).  FP32 accumulates in
-// FP32 for at most kFlushRows rows and is then added into FP64 registers;
-// partial tiles are written in FP64 and summed over slices in fixed order.
-//
-// MFMA 16x16x4 operand layout (lane l = 0..63): A element (i = l % 16,
-// k = l / 16), B element (k = l / 16, j = l % 16).  Accumulator register v
-// holds D(i, j = l % 16) with i = 4 (l / 16) + v for the FP32 instruction and
-// i = l / 16 + 4 v for the FP64 one (checked on the device).
+// Gram products S = A^T B
 // ---------------------------------------------------------------------------
-constexpr int kGT = 64;         // tile edge
-constexpr int kGK = 16;         // rows per LDS panel
-constexpr int kFlushRows = 2048;
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ inline d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-__device__ inline f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-
-template <class T>
-struct AccT;
-template <>
-struct AccT<double> {
-    using V = d4;
-};
-template <>
-struct AccT<float> {
-    using V = f4;
-};
-
-template <class T>
-__global__ void __launch_bounds__(256) gram_kernel(int64_t n_rows, int m, int n, const T* __restrict__ A, int64_t lda,
-                                                   const T* __restrict__ B, int64_t ldb, int64_t rows_per_slice,
-                                                   const int2* __restrict__ tiles, double* __restrict__ part,
-                                                   int64_t part_stride) {
-    using V = typename AccT<T>::V;
-    __shared__ T As[2][kGK][kGT];
-    __shared__ T Bs[2][kGK][kGT];
-    const int2 tile = tiles[blockIdx.x];
-    const int i0 = tile.x * kGT, j0 = tile.y * kGT;
-    const int slice = blockIdx.y;
-    const int64_t r_begin = int64_t(slice) * rows_per_slice;
-    const int64_t r_end = min(n_rows, r_begin + rows_per_slice);
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wi = wave >> 1, wj = wave & 1;
-
-    V acc[2][2];
-    double acc64[2][2][4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            acc[a][b] = V{0, 0, 0, 0};
-            for (int v = 0; v < 4; ++v) acc64[a][b][v] = 0.0;
-        }
-
-    // panel loader: 16 x 64 elements of A and of B, 4 each per thread
-    auto load = [&](int64_t r0, int buf) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = t + 256 * u;        // 0..1023
-            const int rr = e >> 6, cc = e & 63;
-            const int64_t r = r0 + rr;
-            T av = 0, bv = 0;
-            if (r < r_end) {
-                if (i0 + cc < m) av = A[r * lda + i0 + cc];
-                if (j0 + cc < n) bv = B[r * ldb + j0 + cc];
-            }
-            As[buf][rr][cc] = av;
-            Bs[buf][rr][cc] = bv;
-        }
-    };
-
-    int buf = 0;
-    if (r_begin < r_end) load(r_begin, 0);
-    __syncthreads();
-    int64_t since_flush = 0;
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGK) {
-        if (r0 + kGK < r_end) load(r0 + kGK, buf ^ 1);
-#pragma unroll
-        for (int kk = 0; kk < kGK / 4; ++kk) {
-            const int krow = kk * 4 + (lane >> 4);
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const T av = As[buf][krow][wi * 32 + a * 16 + (lane & 15)];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const T bv = Bs[buf][krow][wj * 32 + b * 16 + (lane & 15)];
-                    acc[a][b] = mfma16(av, bv, acc[a][b]);
-                }
-            }
-        }
-        since_flush += kGK;
-        if (!std::is_same<T, double>::value && since_flush >= kFlushRows) {
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    for (int v = 0; v < 4; ++v) acc64[a][b][v] += double(acc[a][b][v]);
-                    acc[a][b] = V{0, 0, 0, 0};
-                }
-            since_flush = 0;
-        }
-        __syncthreads();
-        buf ^= 1;
-    }
-    double* P = part + int64_t(slice) * part_stride;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ii = std::is_same<T, double>::value ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-                const int i = i0 + wi * 32 + a * 16 + ii;
-                const int j = j0 + wj * 32 + b * 16 + (lane & 15);
-                if (i < m && j < n) P[int64_t(i) * n + j] = acc64[a][b][v] + double(acc[a][b][v]);
-            }
-}
-
-// S[i][j] = sum_slices part[s][i][j] (fixed order); mirror when symmetric.
-__global__ void gram_reduce_kernel(int m, int n, int n_slices, const double* __restrict__ part, int64_t part_stride,
-                                   double* __restrict__ S, int64_t lds, int symmetric) {
+// S[i][j] = sum over row slices of part[s][i][j], in FP64 and in slice order;
+// with a symmetric product only i <= j is summed and mirrored, so S is
+// exactly symmetric.
+template <class P>
+__global__ void gram_slices_reduce_kernel(int m, int n, int n_slices, const P* __restrict__ part,
+                                          double* __restrict__ S, int64_t lds, int symmetric) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= int64_t(m) * n) return;
     const int i = int(idx / n), j = int(idx % n);
-    if (symmetric && (i / kGT) > (j / kGT)) return;   // tile not computed; mirrored below
-    double s = 0.0;
-    for (int k = 0; k < n_slices; ++k) s += part[int64_t(k) * part_stride + idx];
-    S[int64_t(i) * lds + j] = s;
-    if (symmetric && (i / kGT) < (j / kGT)) S[int64_t(j) * lds + i] = s;
+    if (symmetric && i > j) return;
+    const int64_t stride = int64_t(m) * n;
+    double acc = 0.0;
+    for (int k = 0; k < n_slices; ++k) acc += double(part[k * stride + idx]);
+    S[int64_t(i) * lds + j] = acc;
+    if (symmetric && i < j) S[int64_t(j) * lds + i] = acc;
 }
+
+static rocblas_status gemm_sb(rocblas_handle h, rocblas_int M, rocblas_int N, rocblas_int K, const float* A,
+                              rocblas_int lda, rocblas_stride sa, const float* B, rocblas_int ldb, rocblas_stride sb,
+                              float* C, rocblas_int ldc, rocblas_stride sc, rocblas_int batch) {
+    const float one = 1.f, zero = 0.f;
+    return rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, M, N, K, &one, A, lda,
+                                         sa, B, ldb, sb, &zero, C, ldc, sc, batch);
+}
+static rocblas_status gemm_sb(rocblas_handle h, rocblas_int M, rocblas_int N, rocblas_int K, const double* A,
+                              rocblas_int lda, rocblas_stride sa, const double* B, rocblas_int ldb, rocblas_stride sb,
+                              double* C, rocblas_int ldc, rocblas_stride sc, rocblas_int batch) {
+    const double one = 1.0, zero = 0.0;
+    return rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, M, N, K, &one, A, lda,
+                                         sa, B, ldb, sb, &zero, C, ldc, sc, batch);
+}
+
+// Gram S = A^T B over n_rows rows.  X^T X is a plain GEMM, so the products of
+// row slices run as one strided-batched rocBLAS GEMM (MFMA, accumulating in
+// the block precision within a slice) into partials that are summed in FP64.
+// Slices: at least kGramMinSliceRows rows, at most kGramMaxSlices of them and
+// kGramPartBytes of partials.
+constexpr int64_t kGramMinSliceRows = 4096;
+constexpr int64_t kGramMaxSlices = 256;
+constexpr size_t kGramPartBytes = size_t(1) << 30;
 
 template <class T>
 void gram_product(chf_ctx* ctx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n_rows, int m, int n,
                   double* S, int64_t lds, hipStream_t s) {
     const bool symmetric = (A == B) && (m == n) && (lda == ldb);
-    const int tm = (m + kGT - 1) / kGT, tn = (n + kGT - 1) / kGT;
-    std::vector<int2> tiles;
-    for (int a = 0; a < tm; ++a)
-        for (int b = 0; b < tn; ++b)
-            if (!symmetric || a <= b) tiles.push_back(make_int2(a, b));
-    // enough workgroups to fill the chip, slices no shorter than 256 rows
-    int64_t n_slices = std::max<int64_t>(1, (2048 + int64_t(tiles.size()) - 1) / int64_t(tiles.size()));
-    n_slices = std::min<int64_t>(n_slices, std::max<int64_t>(1, n_rows / 256));
-    n_slices = std::min<int64_t>(n_slices, 512);
-    int64_t rows_per_slice = (n_rows + n_slices - 1) / n_slices;
-    rows_per_slice = ((rows_per_slice + kGK - 1) / kGK) * kGK;
-    n_slices = (n_rows + rows_per_slice - 1) / rows_per_slice;
-    if (n_slices < 1) n_slices = 1;
-    const int64_t part_stride = int64_t(m) * n;
-    const size_t tile_bytes = ((tiles.size() * sizeof(int2) + 255) / 256) * 256;
-    ctx->scratch2.ensure(tile_bytes + size_t(n_slices) * size_t(part_stride) * sizeof(double));
-    int2* dtiles = reinterpret_cast<int2*>(ctx->scratch2.p);
-    double* part = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch2.p) + tile_bytes);
-    HIP_CHECK(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    dim3 grid(unsigned(tiles.size()), unsigned(n_slices));
-    gram_kernel<T><<<grid, 256, 0, s>>>(n_rows, m, n, A, lda, B, ldb, rows_per_slice, dtiles, part, part_stride);
-    LAUNCH_CHECK();
+    const size_t per = size_t(m) * size_t(n) * sizeof(T);
+    int64_t ns = std::min<int64_t>(kGramMaxSlices, std::max<int64_t>(1, n_rows / kGramMinSliceRows));
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, int64_t(kGramPartBytes / per)));
+    const int64_t R = (n_rows + ns - 1) / ns;               // rows per slice
+    const int64_t nf = n_rows / R;                           // full slices
+    const int64_t tail = n_rows - nf * R;
+    const int64_t n_slices = nf + (tail > 0 ? 1 : 0);
+    CHF_REQUIRE(R <= INT32_MAX && lda <= INT32_MAX && ldb <= INT32_MAX, "gram: dimensions beyond 32-bit BLAS");
+    ctx->scratch2.ensure(size_t(std::max<int64_t>(1, n_slices)) * per);
+    T* part = ctx->scratch2.as<T>();
+    ROCBLAS_CHECK(rocblas_set_stream(ctx->blas, s));
+    // column-major view: part_s (n x m, ld n) = B_s (n x R, ld ldb) * A_s^T
+    if (nf > 0)
+        ROCBLAS_CHECK(gemm_sb(ctx->blas, n, m, rocblas_int(R), B, rocblas_int(ldb), R * ldb, A, rocblas_int(lda),
+                              R * lda, part, n, int64_t(m) * n, rocblas_int(nf)));
+    if (tail > 0)
+        ROCBLAS_CHECK(gemm_sb(ctx->blas, n, m, rocblas_int(tail), B + nf * R * ldb, rocblas_int(ldb), 0,
+                              A + nf * R * lda, rocblas_int(lda), 0, part + nf * int64_t(m) * n, n, 0, 1));
+    if (n_slices == 0) {
+        HIP_CHECK(hipMemsetAsync(part, 0, per, s));
+    }
     const int64_t tot = int64_t(m) * n;
-    gram_reduce_kernel<<<unsigned((tot + 255) / 256), 256, 0, s>>>(m, n, int(n_slices), part, part_stride, S, lds,
-                                                                  symmetric ? 1 : 0);
+    gram_slices_reduce_kernel<T><<<unsigned((tot + 255) / 256), 256, 0, s>>>(
+        m, n, int(std::max<int64_t>(1, n_slices)), part, S, lds, symmetric ? 1 : 0);
     LAUNCH_CHECK();
-    // the host tile list must outlive the async copy
-    HIP_CHECK(hipStreamSynchronize(s));
 }
 
 template void gram_product<float>(chf_ctx*, const float*, int64_t, const float*, int64_t, int64_t, int, int, double*,
@@ -378,11 +281,53 @@ static double* mm_scratch(chf_ctx* ctx, int m, size_t extra_bytes) {
     return ctx->scratch.as<double>();
 }
 
+__global__ void diag_copy_kernel(int m, const double* __restrict__ S, double* __restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) d[i] = S[int64_t(i) * m + i];
+}
+
+// out[0] = min_i R_ii^2 / d_i (the squared sine between column i and the span
+// of the columns before it), out[1] = its index; one workgroup of 256
+__global__ void __launch_bounds__(256) pivot_ratio_kernel(int m, const double* __restrict__ R,
+                                                          const double* __restrict__ d, double* __restrict__ out) {
+    __shared__ double v[256];
+    __shared__ int at[256];
+    double best = 2.0;
+    int bi = 0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const double r = R[int64_t(i) * m + i];
+        const double q = d[i] > 0 ? r * r / d[i] : 1.0;
+        if (q < best) best = q, bi = i;
+    }
+    v[threadIdx.x] = best;
+    at[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w && (v[threadIdx.x + w] < v[threadIdx.x] ||
+                                (v[threadIdx.x + w] == v[threadIdx.x] && at[threadIdx.x + w] < at[threadIdx.x]))) {
+            v[threadIdx.x] = v[threadIdx.x + w];
+            at[threadIdx.x] = at[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = v[0];
+        out[1] = double(at[0]);
+    }
+}
+
+// FP64 blocks: a Cholesky pivot below this fraction of its column's squared
+// norm marks the column as numerically dependent on the ones before it (the
+// factorisation "succeeds" on rounding noise); treated as a breakdown.
+constexpr double kPivotRelF64 = 1e-13;
+
 // Cholesky-QR on one block: S = X^T X, S = R^T R, X <- X R^{-1}.  Returns 0 or
-// the rocSOLVER info (> 0: leading minor not positive definite).
+// the rocSOLVER info (> 0: leading minor not positive definite), or for FP64
+// blocks the 1-based index of a pivot below kPivotRelF64.
 template <class T>
 static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, double shift_rel, hipStream_t s) {
-    double* S = mm_scratch(ctx, m, 0);
+    double* S = mm_scratch(ctx, m, size_t(m) * sizeof(double));
+    double* diag = reinterpret_cast<double*>(reinterpret_cast<char*>(S) + size_t(m) * m * (sizeof(double) + sizeof(float)) + 256);
     gram_product<T>(ctx, X, ldx, X, ldx, n_rows, m, m, S, m, s);
     if (shift_rel > 0) {
         double* tr = reinterpret_cast<double*>(ctx->info.p);
@@ -398,11 +343,24 @@ static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, d
     // column-major U with S = U^T U, i.e. R = U.
     int* dinfo = reinterpret_cast<int*>(reinterpret_cast<char*>(S) + size_t(m) * m * sizeof(double) +
                                         size_t(m) * m * sizeof(float));
+    constexpr bool f64 = std::is_same<T, double>::value;
+    if (f64) {
+        diag_copy_kernel<<<(m + 255) / 256, 256, 0, s>>>(m, S, diag);
+        LAUNCH_CHECK();
+    }
     ROCBLAS_CHECK(rocsolver_dpotrf(ctx->blas, rocblas_fill_upper, m, S, m, dinfo));
+    double piv[2] = {1.0, 0.0};
+    if (f64) {
+        double* pr = reinterpret_cast<double*>(ctx->info.p) + 2;
+        pivot_ratio_kernel<<<1, 256, 0, s>>>(m, S, diag, pr);
+        LAUNCH_CHECK();
+        HIP_CHECK(hipMemcpyAsync(piv, pr, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
     int info = 0;
     HIP_CHECK(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     if (info != 0) return info;
+    if (f64 && !(piv[0] >= kPivotRelF64)) return int(piv[1]) + 1;
     keep_upper_kernel<<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(m, S);
     LAUNCH_CHECK();
     // X is row-major [n_rows][ldx] = column-major Xc [m][n_rows] (ld ldx).

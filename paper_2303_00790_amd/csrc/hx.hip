@@ -676,7 +676,10 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             const int l = lrow + 64 * z;
             // alpha-scaled off-diagonal stencil first; the diagonal, which
             // needs V_eff(p) from memory, is added last
-            V acc;
+            // (the unstaged variant keeps the unscaled form, which needs
+            // fewer registers there: its eight output rows wait in registers
+            // for the KB scatter after the march)
+            V acc = INMARCH ? lz<V>() : lscale(k.c[0], w[z + 6]);
 #pragma unroll
             for (int s = 1; s <= 6; ++s) {
                 V sum = ladd(w[z + 6 - s], w[z + 6 + s]);
@@ -684,7 +687,10 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                 sum = ladd(sum, plane[b][ctr + s][p]);
                 sum = ladd(sum, plane[b][ctr - 20 * s][p]);
                 sum = ladd(sum, plane[b][ctr + 20 * s][p]);
-                acc = s == 1 ? lscale(k.ac[1], sum) : lfma(k.ac[s], sum, acc);
+                if constexpr (INMARCH)
+                    acc = s == 1 ? lscale(k.ac[1], sum) : lfma(k.ac[s], sum, acc);
+                else
+                    acc = lfma(k.c[s], sum, acc);
             }
             const V xc = w[z + 6];
             if (INMARCH && kb) {
@@ -706,8 +712,14 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                     for (int m = 0; m < 4; ++m) acc = lfma(bb[m], cs[m], acc);
                 }
             }
-            const T dg = vr ? T(fma(k.alpha, vr[l], k.d0)) : k.d0;
-            V y = lfma(dg, xc, acc);
+            V y;
+            if constexpr (INMARCH) {
+                const T dg = vr ? T(fma(k.alpha, vr[l], k.d0)) : k.d0;
+                y = lfma(dg, xc, acc);
+            } else {
+                if (vr) acc = lfma(vr[l], xc, acc);
+                y = lscale(k.alpha, lfma(-k.shift, xc, acc));
+            }
             if (Z) y = lfma(-k.beta, zcur, y);
             if (KEEP_R) {
                 r[z] = y;
