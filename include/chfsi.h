@@ -200,6 +200,30 @@ int lanczos_bound(chf_ham* ham, chf_ctx* ctx, const double* v0_dev, int k, doubl
 int gram(chf_ctx* ctx, chf_dtype dtype, const void* A_dev, int64_t lda, const void* B_dev,
          int64_t ldb, int64_t n_rows, int m, int n, double* S_dev, int64_t lds, void* stream);
 
+/* Workspace.  The library keeps device scratch on the handles (KB
+ * coefficients on the Hamiltonian; M x M matrices, Gram partials, Lanczos
+ * vectors and reduction partials on the context) and grows it on first use
+ * at a larger size.  For an operation at nvec vectors of dtype on the
+ * Hamiltonian's grid, chf_workspace_bytes reports the scratch it grows to on
+ * each handle (ldw: the Rayleigh-Ritz work leading dimension, ignored
+ * otherwise); chf_reserve grows it now, so later calls of that operation at
+ * the same or smaller sizes make no device allocation in this library
+ * (rocBLAS / rocSOLVER keep their own workspace on the context's handle,
+ * grown by them on first use).  Operations: */
+enum {
+    CHF_WS_FILTER = 0,          /* ham_apply, chebyshev_filter */
+    CHF_WS_ORTHONORMALIZE = 1,  /* orthonormalize over the grid's n_rows */
+    CHF_WS_RAYLEIGH_RITZ = 2,   /* rayleigh_ritz */
+    CHF_WS_LANCZOS = 3          /* lanczos_bound */
+};
+int chf_workspace_bytes(const chf_ham* ham, int op, chf_dtype dtype, int nvec, int64_t ldw, int64_t* ham_bytes,
+                        int64_t* ctx_bytes);
+/* ctx may be NULL for CHF_WS_FILTER.  CHF_ENOMEM if the device is full. */
+int chf_reserve(chf_ham* ham, chf_ctx* ctx, int op, chf_dtype dtype, int nvec, int64_t ldw);
+/* Device allocations made by the library so far in this process (a counter
+ * for checking that a sequence of calls allocates nothing). */
+int64_t chf_device_allocations(void);
+
 /* Cholesky-QR (paper: the subspace orthonormalisation of ChFSI):
  * S = X^T X (gram), S = R^T R in FP64, X <- X R^{-1} (the update in the block
  * precision).  Breakdown: the factorisation fails, or (FP64 blocks) a pivot

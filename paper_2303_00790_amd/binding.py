@@ -94,6 +94,8 @@ _SIGS = {
     "chf_scf_destroy": [P],
     "scf_step": [P, P, I64, P, I64, C.POINTER(ScfReport), P],
     "chf_scf_get_fields": [P, P, P],
+    "chf_workspace_bytes": [P, INT, INT, INT, I64, P, P],
+    "chf_reserve": [P, P, INT, INT, INT, I64],
     "chf_scf_state_size": [P, P],
     "chf_scf_save": [P, P],
     "chf_scf_load": [P, P, I64],
@@ -135,6 +137,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.chf_last_error.restype = C.c_char_p
         L.chf_last_error.argtypes = []
+        L.chf_device_allocations.restype = C.c_int64
+        L.chf_device_allocations.argtypes = []
         for name, args in _SIGS.items():
             f = getattr(L, name, None)
             if f is None:
@@ -146,7 +150,7 @@ def lib():
 
 
 def declared_symbols() -> list[str]:
-    return ["chf_last_error", *_SIGS.keys()]
+    return ["chf_last_error", "chf_device_allocations", *_SIGS.keys()]
 
 
 def check(rc: int) -> None:
@@ -364,6 +368,24 @@ def rayleigh_ritz(H: Hamiltonian, ctx: Context, X, work, nvec=None) -> np.ndarra
     eig = np.zeros(n, np.float64)
     call("rayleigh_ritz", H.handle, ctx.handle, _dtype_code(X), px, ldx, n, P(eig.ctypes.data), pw, ldw, _stream())
     return eig
+
+
+WS_FILTER, WS_ORTHONORMALIZE, WS_RAYLEIGH_RITZ, WS_LANCZOS = 0, 1, 2, 3
+
+
+def workspace_bytes(H, op: int, dtype: int, nvec: int, ldw: int = 0):
+    """(bytes on the Hamiltonian, bytes on the context) of one operation."""
+    hb, cb = I64(), I64()
+    call("chf_workspace_bytes", H.handle, op, dtype, nvec, ldw, C.byref(hb), C.byref(cb))
+    return hb.value, cb.value
+
+
+def reserve(H, ctx, op: int, dtype: int, nvec: int, ldw: int = 0) -> None:
+    call("chf_reserve", H.handle, ctx.handle if ctx is not None else None, op, dtype, nvec, ldw)
+
+
+def device_allocations() -> int:
+    return int(lib().chf_device_allocations())
 
 
 class Scf:

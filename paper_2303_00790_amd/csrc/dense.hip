@@ -169,19 +169,35 @@ constexpr int64_t kGramMinSliceRows = 4096;
 constexpr int64_t kGramMaxSlices = 256;
 constexpr size_t kGramPartBytes = size_t(1) << 30;
 
+struct GramSlices {
+    int64_t rows;      // rows per slice
+    int64_t full;      // slices of exactly `rows` rows
+    int64_t tail;      // rows of the last, shorter slice (0: none)
+    size_t part_bytes; // partials scratch
+};
+
+static GramSlices gram_slices(int64_t n_rows, int m, int n, size_t elem_bytes) {
+    const size_t per = size_t(m) * size_t(n) * elem_bytes;
+    int64_t ns = std::min<int64_t>(kGramMaxSlices, std::max<int64_t>(1, n_rows / kGramMinSliceRows));
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, int64_t(kGramPartBytes / std::max<size_t>(1, per))));
+    GramSlices g;
+    g.rows = std::max<int64_t>(1, (n_rows + ns - 1) / ns);
+    g.full = n_rows / g.rows;
+    g.tail = n_rows - g.full * g.rows;
+    g.part_bytes = size_t(std::max<int64_t>(1, g.full + (g.tail > 0 ? 1 : 0))) * per;
+    return g;
+}
+
 template <class T>
 void gram_product(chf_ctx* ctx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n_rows, int m, int n,
                   double* S, int64_t lds, hipStream_t s) {
     const bool symmetric = (A == B) && (m == n) && (lda == ldb);
     const size_t per = size_t(m) * size_t(n) * sizeof(T);
-    int64_t ns = std::min<int64_t>(kGramMaxSlices, std::max<int64_t>(1, n_rows / kGramMinSliceRows));
-    ns = std::max<int64_t>(1, std::min<int64_t>(ns, int64_t(kGramPartBytes / per)));
-    const int64_t R = (n_rows + ns - 1) / ns;               // rows per slice
-    const int64_t nf = n_rows / R;                           // full slices
-    const int64_t tail = n_rows - nf * R;
+    const GramSlices g = gram_slices(n_rows, m, n, sizeof(T));
+    const int64_t R = g.rows, nf = g.full, tail = g.tail;
     const int64_t n_slices = nf + (tail > 0 ? 1 : 0);
     CHF_REQUIRE(R <= INT32_MAX && lda <= INT32_MAX && ldb <= INT32_MAX, "gram: dimensions beyond 32-bit BLAS");
-    ctx->scratch2.ensure(size_t(std::max<int64_t>(1, n_slices)) * per);
+    ctx->scratch2.ensure(g.part_bytes);
     T* part = ctx->scratch2.as<T>();
     ROCBLAS_CHECK(rocblas_set_stream(ctx->blas, s));
     // column-major view: part_s (n x m, ld n) = B_s (n x R, ld ldb) * A_s^T
@@ -275,11 +291,17 @@ static int guard(F&& f) {
 
 // S (row-major M x M, FP64) lives at the start of ctx->scratch; the rest holds
 // the cast factor for FP32 updates and rocSOLVER's info word.
+static size_t mm_scratch_bytes(int m, size_t extra_bytes) {
+    return size_t(m) * m * (sizeof(double) + sizeof(float)) + extra_bytes + 256;
+}
 static double* mm_scratch(chf_ctx* ctx, int m, size_t extra_bytes) {
-    const size_t mm = size_t(m) * m * sizeof(double);
-    ctx->scratch.ensure(mm + size_t(m) * m * sizeof(float) + extra_bytes + 256);
+    ctx->scratch.ensure(mm_scratch_bytes(m, extra_bytes));
     return ctx->scratch.as<double>();
 }
+// extra bytes after the M x M matrices: Cholesky-QR keeps the Gram diagonal,
+// Rayleigh-Ritz the eigenvalues and the eigensolver's off-diagonal
+static size_t cholqr_extra(int m) { return size_t(m) * sizeof(double); }
+static size_t rr_extra(int m) { return size_t(m) * sizeof(double) * 2; }
 
 __global__ void diag_copy_kernel(int m, const double* __restrict__ S, double* __restrict__ d) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,7 +348,7 @@ constexpr double kPivotRelF64 = 1e-13;
 // blocks the 1-based index of a pivot below kPivotRelF64.
 template <class T>
 static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, double shift_rel, hipStream_t s) {
-    double* S = mm_scratch(ctx, m, size_t(m) * sizeof(double));
+    double* S = mm_scratch(ctx, m, cholqr_extra(m));
     double* diag = reinterpret_cast<double*>(reinterpret_cast<char*>(S) + size_t(m) * m * (sizeof(double) + sizeof(float)) + 256);
     gram_product<T>(ctx, X, ldx, X, ldx, n_rows, m, m, S, m, s);
     if (shift_rel > 0) {
@@ -403,7 +425,7 @@ template <class T>
 void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double* eig_host, T* W, int64_t ldw,
                             hipStream_t s) {
     const int64_t n_rows = H->grid.n_rows;
-    double* Hs = mm_scratch(ctx, m, size_t(m) * sizeof(double) * 2);
+    double* Hs = mm_scratch(ctx, m, rr_extra(m));
     double* evals = reinterpret_cast<double*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * (sizeof(double) + sizeof(float)) + 256);
     double* E = evals + m;
     int* dinfo = reinterpret_cast<int*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * (sizeof(double) + sizeof(float)));
@@ -447,11 +469,14 @@ void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double*
                                size_t(n_rows), hipMemcpyDeviceToDevice, s));
 }
 
+// three vectors of n_rows as 2-column blocks
+static size_t lanczos_vec_bytes(int64_t n_rows) { return size_t(n_rows) * 2 * 3 * sizeof(double); }
+
 void lanczos_run(chf_ham* H, chf_ctx* ctx, const double* v0, int k, double* out3, hipStream_t s) {
     const int64_t n = H->grid.n_rows;
     // three vectors stored as 2-column blocks (second column zero) so the
     // tiled kernel's 16-byte rows apply
-    ctx->vec.ensure(size_t(n) * 2 * 3 * sizeof(double));
+    ctx->vec.ensure(lanczos_vec_bytes(n));
     double* base = ctx->vec.as<double>();
     HIP_CHECK(hipMemsetAsync(base, 0, size_t(n) * 2 * 3 * sizeof(double), s));
     double* v = base;
@@ -576,6 +601,71 @@ int rayleigh_ritz(chf_ham* H, chf_ctx* ctx, chf_dtype dtype, void* X, int64_t ld
             rayleigh_ritz_t<float>(H, ctx, static_cast<float*>(X), ldx, nvec, eig_host, static_cast<float*>(work), ldw, s);
     });
 }
+
+// device scratch of one operation: on the Hamiltonian (KB coefficients) and on
+// the context (M x M matrices, Gram partials, Lanczos vectors, reductions)
+struct WsNeed {
+    size_t kb = 0, scratch = 0, scratch2 = 0, vec = 0, red = 0;
+};
+
+static WsNeed ws_need(const chf_ham* H, int op, chf_dtype dtype, int nvec, int64_t ldw) {
+    if (!H) fail(CHF_EINVAL, "chf_workspace_bytes: null Hamiltonian");
+    if (dtype != CHF_F32 && dtype != CHF_F64) fail(CHF_EINVAL, "chf_workspace_bytes: bad dtype");
+    if (nvec <= 0) fail(CHF_EINVAL, "chf_workspace_bytes: nvec must be positive");
+    const size_t es = dtype == CHF_F64 ? 8 : 4;
+    const int64_t n_rows = H->grid.n_rows;
+    WsNeed w;
+    switch (op) {
+    case CHF_WS_FILTER:
+        w.kb = kb_coef_bytes(H, nvec, es);
+        break;
+    case CHF_WS_ORTHONORMALIZE:
+        w.scratch = mm_scratch_bytes(nvec, cholqr_extra(nvec));
+        w.scratch2 = gram_slices(n_rows, nvec, nvec, es).part_bytes;
+        break;
+    case CHF_WS_RAYLEIGH_RITZ: {
+        if (ldw <= 0) fail(CHF_EINVAL, "chf_workspace_bytes: Rayleigh-Ritz needs the work leading dimension");
+        const int nb = int(std::min<int64_t>(nvec, ldw));
+        w.kb = kb_coef_bytes(H, nb, es);
+        w.scratch = mm_scratch_bytes(nvec, rr_extra(nvec));
+        w.scratch2 = gram_slices(n_rows, nvec, nb, es).part_bytes;
+        break;
+    }
+    case CHF_WS_LANCZOS:
+        w.kb = kb_coef_bytes(H, 2, sizeof(double));
+        w.vec = lanczos_vec_bytes(n_rows);
+        w.red = kRedBlocks * sizeof(double);
+        break;
+    default:
+        fail(CHF_EINVAL, "chf_workspace_bytes: unknown operation %d", op);
+    }
+    return w;
+}
+
+int chf_workspace_bytes(const chf_ham* H, int op, chf_dtype dtype, int nvec, int64_t ldw, int64_t* ham_bytes,
+                        int64_t* ctx_bytes) {
+    return guard([&] {
+        const WsNeed w = ws_need(H, op, dtype, nvec, ldw);
+        if (ham_bytes) *ham_bytes = int64_t(w.kb);
+        if (ctx_bytes) *ctx_bytes = int64_t(w.scratch + w.scratch2 + w.vec + w.red);
+    });
+}
+
+int chf_reserve(chf_ham* H, chf_ctx* ctx, int op, chf_dtype dtype, int nvec, int64_t ldw) {
+    return guard([&] {
+        const WsNeed w = ws_need(H, op, dtype, nvec, ldw);
+        if ((w.scratch || w.scratch2 || w.vec || w.red) && !ctx) fail(CHF_EINVAL, "chf_reserve: operation needs a context");
+        if (w.kb) H->kb_coef.ensure(w.kb);
+        if (ctx) {
+            ctx->scratch.ensure(w.scratch);
+            ctx->scratch2.ensure(w.scratch2);
+            ctx->vec.ensure(w.vec);
+            ctx->red.ensure(w.red);
+        }
+    });
+}
+
+int64_t chf_device_allocations(void) { return g_device_allocations.load(std::memory_order_relaxed); }
 
 int lanczos_bound(chf_ham* H, chf_ctx* ctx, const double* v0, int k, double* out3, void* stream) {
     return guard([&] {

@@ -877,10 +877,14 @@ bool tiled_ok(const chf_ham* H, const void* X, int64_t ldx, const void* Y, int64
     return true;
 }
 
+size_t kb_coef_bytes(const chf_ham* H, int nvec, size_t elem_bytes) {
+    return size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * elem_bytes;
+}
+
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
              double shift, double beta, hipStream_t s, int force_kernel, bool lap_only) {
-    H->kb_coef.ensure(size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * sizeof(T));
+    H->kb_coef.ensure(kb_coef_bytes(H, nvec, sizeof(T)));
     T* C = H->kb_coef.as<T>();
     if (H->proj.n_proj > 0 && !lap_only) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, C, s); });
     const bool tiled = force_kernel != 1 && tiled_ok<T>(H, X, ldx, Y, ldy, Z, ldz, nvec);

@@ -5,6 +5,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <atomic>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -50,6 +51,9 @@ void set_last_error(const char* msg);
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
+// device allocations made by the library so far (all handles, all devices)
+inline std::atomic<int64_t> g_device_allocations{0};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -71,6 +75,7 @@ struct DevBuf {
             fail(CHF_ENOMEM, "device allocation of %zu bytes failed", n);
         }
         bytes = n;
+        g_device_allocations.fetch_add(1, std::memory_order_relaxed);
     }
     void ensure(size_t n) {
         if (n > bytes) alloc(n);

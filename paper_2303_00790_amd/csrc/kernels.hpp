@@ -15,6 +15,9 @@ template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
              double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false);
 
+// bytes of the KB coefficient scratch an H X launch on nvec vectors needs
+size_t kb_coef_bytes(const chf_ham* H, int nvec, size_t elem_bytes);
+
 void timer_enable(int on);
 void timer_read(double* ms, int64_t* launches);
 

@@ -130,3 +130,32 @@ def test_chfsi_iteration_f64(system):
         eig = s["B"].rayleigh_ritz(s["Hg"], s["ctx"], Xg, W)
         assert np.abs(eig - lam).max() < 1e-9
         a, a0 = lam[-1], lam[0]
+
+
+def test_reserved_workspace_makes_later_calls_allocation_free(system):
+    """After chf_reserve for an operation, calling it at that size allocates
+    no device memory in the library (the counter of its allocations stays)."""
+    s = system
+    B = s["B"]
+    H = s["Hg"]
+    ctx = B.Context(0)
+    X = to_rows(s, random_block(s["g"].n, 48, 2403), torch.float64)
+    W = torch.zeros_like(X)
+    v0 = to_rows(s, random_block(s["g"].n, 1, 3003)[:, 0], torch.float64)
+    # the query is consistent and non-trivial
+    hb, cb = B.workspace_bytes(H, B.WS_ORTHONORMALIZE, B.CHF_F64, 48)
+    assert hb == 0 and cb >= 48 * 48 * 12
+    hb, cb = B.workspace_bytes(H, B.WS_FILTER, B.CHF_F64, 48)
+    assert hb >= 4 * H.n_proj * 48 * 8 and cb == 0
+    with pytest.raises(B.ChfError):
+        B.workspace_bytes(H, 7, B.CHF_F64, 48)
+    for op, ldw in ((B.WS_FILTER, 0), (B.WS_ORTHONORMALIZE, 0), (B.WS_RAYLEIGH_RITZ, 48), (B.WS_LANCZOS, 0)):
+        B.reserve(H, ctx, op, B.CHF_F64, 48, ldw)
+    before = B.device_allocations()
+    b, tmin, _ = H.lanczos_bound(ctx, v0, 10)
+    H.apply(X, W)
+    H.filter(X, W, 4, tmin + 0.1 * (b - tmin), b, tmin - 1.0)
+    B.orthonormalize(ctx, X)
+    B.rayleigh_ritz(H, ctx, X, W)
+    torch.cuda.synchronize()
+    assert B.device_allocations() == before
