@@ -6,6 +6,7 @@ in the first SCF step and one in every later step.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -59,20 +60,40 @@ def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nve
     return dict(H=H, ctx=ctx, prm=prm, X=X, W=torch.zeros_like(X), v0=v0, rows=rows, ne=ne, M=M)
 
 
-def run(state, rho0, max_steps: int = 60, sre_tol_ry: float = 1e-4, min_steps: int = 1, log=None) -> ScfResult:
+def run(state, rho0, max_steps: int = 60, sre_tol_ry: float = 1e-4, min_steps: int = 1, log=None,
+        trace=None) -> ScfResult:
     """SCF steps until SRE < sre_tol_ry; ``log`` (optional) receives one
-    line per step."""
+    line per step; ``trace`` (optional path or writable text file) receives
+    one JSON object per step: the step report (SRE, energies, HOMO/LUMO,
+    filter bounds, ChFSI and CG iterations, Cholesky-QR fallbacks) and the
+    step's wall time in seconds."""
+    import json
+    import time
+    import torch
     scf = B.Scf(state["H"], state["ctx"], state["prm"], rho0, state["v0"])
     reps = []
     eig = None
     converged = False
-    for _ in range(max_steps):
-        rep, eig = scf.step(state["X"], state["W"])
-        reps.append(rep.as_dict())
-        if log is not None:
-            log(f"  scf step {rep.step}: SRE {rep.sre_ry:.3e} Ry, E {rep.energy:.8f} Ha")
-        if rep.sre_ry < sre_tol_ry and rep.step >= min_steps:
-            converged = True
-            break
+    own = isinstance(trace, (str, bytes, os.PathLike))
+    tf = open(trace, "a") if own else trace
+    try:
+        for _ in range(max_steps):
+            t0 = time.perf_counter()
+            rep, eig = scf.step(state["X"], state["W"])
+            torch.cuda.synchronize()
+            d = rep.as_dict()
+            d["seconds"] = time.perf_counter() - t0
+            reps.append(d)
+            if tf is not None:
+                tf.write(json.dumps(d) + "\n")
+                tf.flush()
+            if log is not None:
+                log(f"  scf step {rep.step}: SRE {rep.sre_ry:.3e} Ry, E {rep.energy:.8f} Ha")
+            if rep.sre_ry < sre_tol_ry and rep.step >= min_steps:
+                converged = True
+                break
+    finally:
+        if own:
+            tf.close()
     state["scf"] = scf
     return ScfResult(len(reps), converged, reps[-1]["energy"], eig, reps)

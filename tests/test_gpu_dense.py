@@ -1,11 +1,13 @@
-"""GPU parity of the dense ChFSI steps (MFMA Gram products, Lanczos bound,
+"""GPU parity of the dense ChFSI steps (Gram products, Lanczos bound,
 Cholesky-QR, Rayleigh-Ritz, one full ChFSI iteration) against the FP64
 oracle, through the C ABI.
 
 Tolerances: FP64 Gram 1e-13 relative (the products are exact dot products in
-a different summation order); FP32 Gram 2e-6 relative to |A||B| (FP32
-accumulation over at most 2048 rows, eps_32 * sqrt(2048) ~ 3e-6 worst-case
-random-walk, partials added in FP64).  Eigenvalues from FP64 paths 1e-10 Ha.
+a different summation order); FP32 Gram 2e-6 of n (the scale of the diagonal):
+FP32 accumulation within row slices of about 4100-5000 rows here,
+eps_32 * sqrt(R) ~ 4e-6 random-walk relative error per slice sum, the slice
+partials added in FP64 (for the 70000-row case 17 slices, averaging the
+slice errors down by ~sqrt(17)).  Eigenvalues from FP64 paths 1e-10 Ha.
 """
 import numpy as np
 import pytest
@@ -159,3 +161,18 @@ def test_reserved_workspace_makes_later_calls_allocation_free(system):
     B.rayleigh_ritz(H, ctx, X, W)
     torch.cuda.synchronize()
     assert B.device_allocations() == before
+
+
+def test_absurd_reservation_reports_out_of_memory(system):
+    """A workspace far beyond the device (2^30 FP64 vectors of KB
+    coefficients) fails with CHF_ENOMEM and leaves the handle usable."""
+    s = system
+    B = s["B"]
+    with pytest.raises(B.ChfError) as e:
+        B.reserve(s["Hg"], None, B.WS_FILTER, B.CHF_F64, 1 << 30)
+    assert e.value.code == -2
+    X = to_rows(s, random_block(s["g"].n, 8, 2404), torch.float64)
+    Y = torch.zeros_like(X)
+    s["Hg"].apply(X, Y)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Y).all())

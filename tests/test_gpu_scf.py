@@ -159,3 +159,21 @@ def test_checkpoint_resume_is_bit_exact(si35):
         other.load(state)
     with pytest.raises(B.ChfError):
         fresh.load(state[:-1])
+
+
+def test_run_writes_one_json_record_per_step(tmp_path):
+    """The SCF driver's trace: one JSON object per step with the step report
+    and its wall time."""
+    import json
+    from paper_2303_00790_amd import scf as S
+    c = make_cluster(5.5, 1001)
+    st = S.setup(c, OH.PseudoParams(), h=0.7, dtype="f64", degree=10)
+    rho = st["H"].sad_density(c.pos, c.species, c.n_electrons)
+    path = tmp_path / "scf_trace.jsonl"
+    res = S.run(st, rho, max_steps=3, sre_tol_ry=0.0, trace=str(path))
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert res.steps == 3 and [r["step"] for r in recs] == [1, 2, 3]
+    for r in recs:
+        assert r["seconds"] > 0 and math.isfinite(r["energy"]) and r["sre_ry"] > 0
+        assert r["chfsi_iters"] == (4 if r["step"] == 1 else 1)
+        assert r["bound_a0"] < r["bound_a"] < r["bound_b"]
