@@ -87,7 +87,23 @@ def cpu_baseline(degree: int, sample: str = "auto", workload: str = "d16nm") -> 
     dt = time.perf_counter() - t0
     return {"value": g.n * nvec / dt, "unit": "gridpt*vectors/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle degree-{degree} filter, {wl.name} grid ({g.n} points) x {nvec} vectors "
-                      f"(scipy CSR SpMM, single-threaded), {dt:.1f} s"}
+                      f"(scipy sparse stencil and projector products, single-threaded), {dt:.1f} s "
+                      f"on {host_cpu()}"}
+
+
+def host_cpu() -> str:
+    """CPU model and visible logical CPUs of the host running the oracle."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return f"{model}, {n} logical CPUs visible
 
 
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix peaks

@@ -143,3 +143,35 @@ def test_scf_energy_stationary(sih4_scf):
     sre = np.array([r.sre_ry for r in reps])
     late = slice(10, None)
     assert np.all(np.abs(e[late] - e[-1]) < 10 * sre[late] ** 2 + 1e-8)
+
+
+def test_resume_from_saved_state_is_bit_exact(tmp_path):
+    """What an SCF carries between steps (rho_in, V_H warm start, X, filter
+    bounds, step counter, Anderson history) saved to .npz and loaded into a
+    fresh state reproduces the next step exactly."""
+    d = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
+    pos = np.array([[0, 0, 0], [d, d, d], [d, -d, -d], [-d, d, -d], [-d, -d, d]], float)
+    species = np.array([0, 1, 1, 1, 1], np.int32)
+    g = G.build_grid(float(np.sqrt((pos ** 2).sum(1)).max()) + 5.0, 0.7)
+    nbr = G.neighbour_table(g)
+    pp = OH.PseudoParams()
+    H = OH.build_hamiltonian(g, pos, species, pp)
+    eii = S.ion_energy(pos, pp.charges(species))
+    v0 = random_block(g.n, 1, 6)[:, 0]
+    st = S.ScfState(S.sad_density(g, pos, species, 8), random_block(g.n, 10, 5), np.zeros(g.n))
+    for _ in range(3):
+        S.scf_step(H, nbr, st, 8, 12, v0, eii)
+    f = tmp_path / "state.npz"
+    np.savez(f, rho_in=st.rho_in, X=st.X, vh=st.vh, a=st.a, a0=st.a0, step=st.step,
+             beta=st.mixer.beta, history=st.mixer.history, xs=np.array(st.mixer.xs), fs=np.array(st.mixer.fs))
+    z = np.load(f)
+    mixer = S.Anderson(float(z["beta"]), int(z["history"]))
+    mixer.xs, mixer.fs = [x.copy() for x in z["xs"]], [x.copy() for x in z["fs"]]
+    resumed = S.ScfState(z["rho_in"].copy(), z["X"].copy(), z["vh"].copy(), float(z["a"]), float(z["a0"]),
+                         int(z["step"]), mixer)
+    r1 = S.scf_step(H, nbr, st, 8, 12, v0, eii)
+    r2 = S.scf_step(H, nbr, resumed, 8, 12, v0, eii)
+    assert r1.step == r2.step == 4
+    assert r1.energy == r2.energy and r1.sre_ry == r2.sre_ry
+    assert np.array_equal(r1.eig, r2.eig)
+    assert np.array_equal(st.rho_in, resumed.rho_in) and np.array_equal(st.X, resumed.X)
