@@ -103,7 +103,7 @@ def host_cpu() -> str:
     except OSError:
         pass
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    return f"{model}, {n} logical CPUs visible
+    return f"{model}, {n} logical CPUs visible"
 
 
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix peaks
