@@ -182,7 +182,9 @@ int chf_filter_generic(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, 
  * the launch stream around every H X launch (slot 0) and every KB-gather
  * launch (slot 1).  chf_timer(1) clears and enables, chf_timer(0) disables;
  * chf_timer_read synchronises the device and returns per slot the summed
- * milliseconds (ms_host[2]) and the launch counts (launches_host[2]). */
+ * milliseconds (ms_host[2]) and the launch counts (launches_host[2]).  The
+ * timer is process-wide and thread-safe; its events belong to the device
+ * current at each launch, so read it with that device current. */
 int chf_timer(int enable);
 int chf_timer_read(double* ms_host, int64_t* launches_host);
 

@@ -15,7 +15,9 @@
 //                     workgroup per (8^3 block, 32-float / 16-double vector
 //                     chunk), z-march with a 13-deep register window per
 //                     column, x/y halos staged in LDS (double-buffered).
+#include <atomic>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -824,7 +826,7 @@ void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, con
 // around every H X and KB-gather launch while enabled
 // ---------------------------------------------------------------------------
 struct KernelTimer {
-    bool on = false;
+    std::atomic<bool> on{false};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[2];   // 0: H X, 1: KB gather
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
@@ -848,17 +850,24 @@ struct KernelTimer {
     }
 };
 static KernelTimer g_timer;
+static std::mutex g_timer_mu;   // guards the event pool and the spans
 
 template <class F>
 static void timed(int which, hipStream_t s, F&& launch) {
-    if (!g_timer.on) {
+    if (!g_timer.on.load(std::memory_order_relaxed)) {
         launch();
         return;
     }
-    hipEvent_t a = g_timer.get(), b = g_timer.get();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_timer_mu);
+        a = g_timer.get();
+        b = g_timer.get();
+    }
     HIP_CHECK(hipEventRecord(a, s));
     launch();
     HIP_CHECK(hipEventRecord(b, s));
+    std::lock_guard<std::mutex> lk(g_timer_mu);
     g_timer.spans[which].emplace_back(a, b);
 }
 
@@ -897,12 +906,14 @@ void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z,
 }
 
 void timer_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
     g_timer.recycle();
-    g_timer.on = on != 0;
+    g_timer.on.store(on != 0, std::memory_order_relaxed);
 }
 
 void timer_read(double* ms, int64_t* launches) {
     HIP_CHECK(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(g_timer_mu);
     for (int w = 0; w < 2; ++w) {
         double t = 0;
         for (auto& p : g_timer.spans[w]) {

@@ -89,19 +89,27 @@ __global__ void lda_kernel(int64_t n, const double* __restrict__ rho, double* __
 // Moments: M[a][b][c] = h^3 sum_p rho_p x^a y^b z^c, a + b + c <= 4.
 // ---------------------------------------------------------------------------
 constexpr int kNMom = 35;
-__constant__ int c_mom_exp[kNMom][3];
 
-static void mom_exponents(int out[kNMom][3]) {
+// exponents (a, b, c) of the Cartesian moments x^a y^b z^c, a + b + c <= 4,
+// by order, built at compile time into constant memory (every device gets
+// the table with the code object)
+struct MomExp {
+    int e[kNMom][3];
+};
+constexpr MomExp make_mom_exponents() {
+    MomExp t{};
     int k = 0;
     for (int n = 0; n <= 4; ++n)
         for (int a = n; a >= 0; --a)
             for (int b = n - a; b >= 0; --b) {
-                out[k][0] = a;
-                out[k][1] = b;
-                out[k][2] = n - a - b;
+                t.e[k][0] = a;
+                t.e[k][1] = b;
+                t.e[k][2] = n - a - b;
                 ++k;
             }
+    return t;
 }
+__constant__ MomExp c_mom = make_mom_exponents();
 
 __global__ void __launch_bounds__(256) moments_kernel(int64_t n_rows, const int32_t* __restrict__ ijk4, double h,
                                                       const double* __restrict__ rho, double* __restrict__ part) {
@@ -116,7 +124,7 @@ __global__ void __launch_bounds__(256) moments_kernel(int64_t n_rows, const int3
         double px[5] = {1, x, x * x, x * x * x, x * x * x * x};
         double py[5] = {1, y, y * y, y * y * y, y * y * y * y};
         double pz[5] = {1, z, z * z, z * z * z, z * z * z * z};
-        for (int m = 0; m < kNMom; ++m) acc[m] += q * px[c_mom_exp[m][0]] * py[c_mom_exp[m][1]] * pz[c_mom_exp[m][2]];
+        for (int m = 0; m < kNMom; ++m) acc[m] += q * px[c_mom.e[m][0]] * py[c_mom.e[m][1]] * pz[c_mom.e[m][2]];
     }
     for (int m = 0; m < kNMom; ++m) {
         sh[threadIdx.x] = acc[m];
@@ -379,13 +387,6 @@ int hartree_solve(chf_ham* H, chf_ctx* ctx, const double* rho, double* vh, doubl
     double* M = vg + std::max<int64_t>(1, H->n_ghost);
     double* ck = M + 64;
     ctx->red.ensure(size_t(1024) * kNMom * sizeof(double));
-    static bool exp_ready = false;
-    if (!exp_ready) {
-        int e[kNMom][3];
-        mom_exponents(e);
-        HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_mom_exp), e, sizeof(e)));
-        exp_ready = true;
-    }
     const double h = H->h;
     // moments
     const int mb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)));
