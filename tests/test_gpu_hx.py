@@ -79,7 +79,7 @@ def test_ordering_and_vloc(system):
 
 @pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
-@pytest.mark.parametrize("m,ld", [(64, 64), (36, 40), (8, 8)])
+@pytest.mark.parametrize("m,ld", [(64, 64), (36, 40), (8, 8), (5, 8), (5, 5), (1, 1)])
 def test_apply_parity(system, generic, dtype, tol, m, ld):
     s = system
     X = random_block(s["g"].n, m, 2001 + m)
