@@ -477,7 +477,10 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
     // LDS plane: the full 20 x 20 square x in [-6, 14), y in [-6, 14) (corners
     // unused) so every neighbour is a constant offset from the centre
     __shared__ V plane[2][400][LANES];
-    __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][LANES][4];
+    // staged KB coefficients [atom slot][channel pair][lane][2]: a lane's two
+    // channels of a pair are adjacent, so one 16-byte read per pair with a
+    // 16-byte lane stride (conflict-free across the 16 lanes of a column)
+    __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][2][LANES][2];
 
     // XCD-aware tile order: workgroup ids are dealt round-robin to the 8
     // XCDs; give each XCD a contiguous run of the tile sequence (blocks in
@@ -644,7 +647,7 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             for (int u = 0; u < 4; ++u) {
                 const int e = t + NT * u;
                 const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
-                if (sl < kMaxBlockAtoms) cst[sl][lp][lm] = cstage[u];
+                if (sl < kMaxBlockAtoms) cst[sl][lm >> 1][lp][lm & 1] = cstage[u];
             }
         }
         __syncthreads();
@@ -702,16 +705,19 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                     constexpr int kk = decltype(kc)::value;
                     if (kk < cnt) {
                         const int sl = row_bcast<kk>(e_slot[z]);
-                        const V* cs = &cst[sl][p][0];
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) acc = lfma(row_bcast<kk>(e_b[z][m]), cs[m], acc);
+                        const V* c01 = &cst[sl][0][p][0];
+                        const V* c23 = &cst[sl][1][p][0];
+                        acc = lfma(row_bcast<kk>(e_b[z][0]), c01[0], acc);
+                        acc = lfma(row_bcast<kk>(e_b[z][1]), c01[1], acc);
+                        acc = lfma(row_bcast<kk>(e_b[z][2]), c23[0], acc);
+                        acc = lfma(row_bcast<kk>(e_b[z][3]), c23[1], acc);
                     }
                 });
                 for (int en = e_lo[z] + 16; en < e_hi[z]; ++en) {     // rows with more than 16 entries
                     const T* bb = ent_beta + 4 * int64_t(en);
-                    const V* cs = &cst[ent_slot[en]][p][0];
+                    const int sl = ent_slot[en];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) acc = lfma(bb[m], cs[m], acc);
+                    for (int m = 0; m < 4; ++m) acc = lfma(bb[m], cst[sl][m >> 1][p][m & 1], acc);
                 }
             }
             V y;
@@ -756,10 +762,10 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
                             V c0, c1, c2, c3;
                             if (STAGE) {
                                 const int sl = ent_slot[en];
-                                c0 = cst[sl][p][0];
-                                c1 = cst[sl][p][1];
-                                c2 = cst[sl][p][2];
-                                c3 = cst[sl][p][3];
+                                c0 = cst[sl][0][p][0];
+                                c1 = cst[sl][0][p][1];
+                                c2 = cst[sl][1][p][0];
+                                c3 = cst[sl][1][p][1];
                             } else {
                                 const T* ca = C + int64_t(ent_atom[en]) * 4 * int64_t(nvec) + vbase;
                                 c0 = *reinterpret_cast<const V*>(ca);
