@@ -700,13 +700,16 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             const V xc = w[z + 6];
             if (INMARCH && kb) {
                 // KB term of row z: sum over its entries of h_l beta_lm C_lm
+                // (slot offsets added to a per-lane base: the array's LDS
+                // address is beyond the 16-bit offset field)
+                const V* cst_lane = &cst[0][0][p][0];
                 const int cnt = e_hi[z] - e_lo[z];
                 static_for<0, 16>([&](auto kc) {
                     constexpr int kk = decltype(kc)::value;
                     if (kk < cnt) {
                         const int sl = row_bcast<kk>(e_slot[z]);
-                        const V* c01 = &cst[sl][0][p][0];
-                        const V* c23 = &cst[sl][1][p][0];
+                        const V* c01 = cst_lane + sl * (4 * LANES);
+                        const V* c23 = c01 + 2 * LANES;
                         acc = lfma(row_bcast<kk>(e_b[z][0]), c01[0], acc);
                         acc = lfma(row_bcast<kk>(e_b[z][1]), c01[1], acc);
                         acc = lfma(row_bcast<kk>(e_b[z][2]), c23[0], acc);
