@@ -65,3 +65,48 @@ WORKLOADS = {
     "d16nm": Workload("d16nm", "16 nm Si107041H9060, one degree-16 FP32 filter pass on 256 vectors", 80.0, 5,
                       degree=16, nvec=256, dtype="f32"),
 }
+
+
+# Constants of the method shared by every workload (the readings of the
+# paper's silent points; the defaults the drivers use).
+METHOD = {
+    "fd_half_order": 6,                 # 12th-order central second derivative, 37-point star
+    "block_edge": 8,                    # Hilbert blocks of 8^3 points
+    "domain_margin_bohr": 6.0,          # R_domain = max |r_atom| + margin
+    "lanczos_steps": 10,
+    "chfsi_iters_first_scf_step": 4,
+    "chfsi_iters_later_scf_steps": 1,
+    "sre_tol_ry": 1e-4,
+    "states": "roundup64(ceil(1.1 * n_electrons / 2))",
+    "anderson_beta": 0.1,
+    "anderson_history": 8,
+    "poisson_cg_rtol": 1e-12,
+    "multipole_lmax": 4,
+    "lda": "PZ81 unpolarised",
+    "bond_si_h_angstrom": 1.48,
+    "lattice_angstrom": 5.43,
+    "lattice_table_i_angstrom": 5.38,
+}
+
+
+def as_config() -> dict:
+    """Every workload with its seeds, the model pseudopotential and the
+    method constants, as one JSON-ready dictionary (written to
+    synth/workloads.json by ``python -m synth.workloads``)."""
+    import dataclasses
+    wl = {}
+    for name, w in WORKLOADS.items():
+        d = dataclasses.asdict(w)
+        d.update(geometry_seed=w.geometry_seed, x_seed=w.x_seed, lanczos_seed=w.lanczos_seed)
+        wl[name] = d
+    return {"workloads": wl, "model_pseudopotential": dataclasses.asdict(MODEL_PP), "method": dict(METHOD)}
+
+
+if __name__ == "__main__":
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
+    with open(path, "w") as f:
+        json.dump(as_config(), f, indent=1)
+        f.write("\n")
+    print(path)
