@@ -274,13 +274,14 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
                 at[size_t(4 * a + 3)] = si ? pp->z_si : pp->z_h;
                 wd[size_t(a)] = si ? pp->r_loc_si : pp->r_loc_h;
             }
-            DevBuf dat, dwd, bad;
+            DevBuf dat, dwd;
             upload(dat, at, s);
             upload(dwd, wd, s);
             launch_vloc(H.get(), dat.as<double4>(), dwd.as<double>(), atoms->n_atoms, s);
-            bad.alloc(sizeof(int));
-            HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-            launch_cast_veff(H.get(), H->vloc.as<double>(), H->veff64.as<double>(), H->veff32.as<float>(), bad.as<int>(), s);
+            H->flag.alloc(256);
+            HIP_CHECK(hipMemsetAsync(H->flag.p, 0, sizeof(int), s));
+            launch_cast_veff(H.get(), H->vloc.as<double>(), H->veff64.as<double>(), H->veff32.as<float>(),
+                             H->flag.as<int>(), s);
             HIP_CHECK(hipStreamSynchronize(s));
         }
         *out = H.release();
@@ -378,16 +379,14 @@ int ham_set_veff(chf_ham* H, const double* veff_dev, void* stream) {
         CHF_REQUIRE(H && veff_dev, "ham_set_veff: null argument");
         check_device(H);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        DevBuf bad;
-        bad.alloc(sizeof(int));
-        HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        HIP_CHECK(hipMemsetAsync(H->flag.p, 0, sizeof(int), s));
         // validate first (no writes), then cast
-        launch_cast_veff(H, veff_dev, nullptr, nullptr, bad.as<int>(), s);
+        launch_cast_veff(H, veff_dev, nullptr, nullptr, H->flag.as<int>(), s);
         int hbad = 0;
-        HIP_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(&hbad, H->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         if (hbad) fail(CHF_ENONFINITE, "ham_set_veff: NaN or Inf in V_eff");
-        launch_cast_veff(H, veff_dev, H->veff64.as<double>(), H->veff32.as<float>(), bad.as<int>(), s);
+        launch_cast_veff(H, veff_dev, H->veff64.as<double>(), H->veff32.as<float>(), H->flag.as<int>(), s);
     });
 }
 

@@ -180,6 +180,7 @@ struct chf_ham {
     chf::DevBuf sup_beta64, ent_beta64;  // double [pairs][4]
     chf::DevBuf sup_beta32, ent_beta32;  // float  [pairs][4]
     chf::DevBuf kb_coef;        // KB coefficients scratch [4 n_proj][nvec] in the work dtype
+    chf::DevBuf flag;           // int: set by the V_eff cast when a value is NaN or Inf
     int dtypes = 0;
     bool has_nbr = false;
     // Poisson exterior stencil points (built on first use, scf.hip)

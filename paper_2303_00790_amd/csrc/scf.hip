@@ -637,10 +637,12 @@ static void scf_step_t(chf_scf* S, T* X, int64_t ldx, T* W, int64_t ldw, chf_scf
     axpbypcz_kernel<<<nblk(n), 256, 0, s>>>(n, 1.0, H->vloc.as<double>(), 1.0, S->f(F_VH), 1.0, S->f(F_VXC), S->f(F_VEFF));
     LAUNCH_CHECK();
     {
-        DevBuf bad;
-        bad.alloc(sizeof(int));
-        HIP_CHECK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-        launch_cast_veff(H, S->f(F_VEFF), H->veff64.as<double>(), H->veff32.as<float>(), bad.as<int>(), s);
+        HIP_CHECK(hipMemsetAsync(H->flag.p, 0, sizeof(int), s));
+        launch_cast_veff(H, S->f(F_VEFF), H->veff64.as<double>(), H->veff32.as<float>(), H->flag.as<int>(), s);
+        int hbad = 0;
+        HIP_CHECK(hipMemcpyAsync(&hbad, H->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (hbad) fail(CHF_ENONFINITE, "scf_step: NaN or Inf in V_eff");
     }
     double bounds[3];
     lanczos_run(H, ctx, S->f(F_VL), S->prm.lanczos_k, bounds, s);
