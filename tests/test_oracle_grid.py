@@ -9,34 +9,43 @@ import pytest
 from oracle import grid as G
 from synth.cluster import (A_SI_OPTIMISED, make_cluster, silicon_cluster_counts, n_states,
                            BOHR_ANGSTROM)
+from golden import table_i, text_figures
 
 
-# Table I of the paper lists (N_Si, N_H) per nanocluster.  With an atom-centred
-# sphere, two-neighbour pruning and one H per dangling bond, four of its rows
-# are reproduced exactly; each row holds on an interval of R / a, and the
-# midpoints are used.  (Rows Si1947H604 and Si10869H1924 are not reproducible
-# by this rule and are not pins.)
-TABLE_I = [((4.91808 + 4.94975) / 2, 4001, 1012),
-           ((8.84237 + 8.86002) / 2, 23049, 3220),
-           ((11.51086 + 11.51901) / 2, 51071, 5484)]
+# Table I of the paper lists (N_Si, N_H) per nanocluster (tests/golden/table_i.txt).
+# With an atom-centred sphere, two-neighbour pruning and one H per dangling bond,
+# four of its rows are reproduced exactly; each row holds on an interval of R / a,
+# and the midpoints below are used.  (Rows Si1947H604 and Si10869H1924 are not
+# reproducible by this rule and are not pins.)
+R_OVER_A = {"Si4001H1012": (4.91808 + 4.94975) / 2,
+            "Si23049H3220": (8.84237 + 8.86002) / 2,
+            "Si51071H5484": (11.51086 + 11.51901) / 2,
+            "Si107641H9084": (14.75424 + 14.76482) / 2}
+ROWS = {r.name: r for r in table_i()}
+FAST = ["Si4001H1012", "Si23049H3220", "Si51071H5484"]
 
 
-@pytest.mark.parametrize("r_over_a,n_si,n_h", TABLE_I)
-def test_table_i_counts(r_over_a, n_si, n_h):
-    si, dangling = silicon_cluster_counts(r_over_a)
-    assert (len(si), len(dangling)) == (n_si, n_h)
+@pytest.mark.parametrize("name", FAST)
+def test_table_i_counts(name):
+    si, dangling = silicon_cluster_counts(R_OVER_A[name])
+    assert (len(si), len(dangling)) == (ROWS[name].n_si, ROWS[name].n_h)
 
 
 @pytest.mark.slow
 def test_table_i_largest():
-    si, dangling = silicon_cluster_counts((14.75424 + 14.76482) / 2)
-    assert (len(si), len(dangling)) == (107641, 9084)
+    name = "Si107641H9084"
+    si, dangling = silicon_cluster_counts(R_OVER_A[name])
+    assert (len(si), len(dangling)) == (ROWS[name].n_si, ROWS[name].n_h)
 
 
-def test_table_i_diameters():
-    # at a = 5.38 angstrom the four reproduced rows' diameters are 5.3, 9.6, 12.5, 16.0 nm
-    for (r, _, _), d in zip(TABLE_I, (5.3, 9.6, 12.5)):
-        assert abs(2 * r * A_SI_OPTIMISED / 10 - d) < 0.15
+def test_table_i_lattice_constant():
+    assert A_SI_OPTIMISED == text_figures()["lattice_optimised_angstrom"]
+
+
+@pytest.mark.parametrize("name", sorted(R_OVER_A))
+def test_table_i_diameters(name):
+    # the cut sphere's diameter at a = 5.38 angstrom is the printed one to its last digit
+    assert abs(2 * R_OVER_A[name] * A_SI_OPTIMISED / 10 - ROWS[name].diameter_nm) < 0.15
 
 
 def test_hydrogen_count_is_missing_bonds():
@@ -56,8 +65,8 @@ def test_hydrogen_count_is_missing_bonds():
 
 def test_states_are_multiples_of_64():
     # Table I's state counts are all multiples of 64 and exceed the occupied count
-    for n_si, n_h, m in [(4001, 1012, 9216), (107641, 9084, 245760)]:
-        assert m % 64 == 0 and m >= (4 * n_si + n_h) // 2
+    for r in table_i():
+        assert r.states % 64 == 0 and r.states >= (4 * r.n_si + r.n_h) // 2
     assert n_states(4 * 35 + 36) == 128
 
 
