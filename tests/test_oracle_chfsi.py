@@ -101,3 +101,24 @@ def test_chfsi_converges_to_lowest_eigenvalues(tiny):
         a, a0 = ritz[-1], ritz[0]
     # the lowest 8 of the 10 tracked values converge (the top two guard the gap)
     assert np.allclose(ritz[:8], lam[:8], atol=1e-10)
+
+
+@pytest.mark.parametrize("m,a,b,a0", [(1, -0.2, 3.0, -1.0), (12, 0.1, 40.0, -0.5), (16, -2.0, 5.0, -2.3)])
+def test_filter_scalars_are_chebyshev_ratios(m, a, b, a0):
+    # dividing T_{k}(t) = 2 t T_{k-1}(t) - T_{k-2}(t) by T_k(t0), t = (x - c) / e, gives
+    # alpha_k = 2 T_{k-1}(t0) / (e T_k(t0)) (alpha_1 = 1 / (e t0)) and beta_k = T_{k-2}(t0) / T_k(t0);
+    # the T_k(t0) here come from numpy's Chebyshev series evaluation
+    e, c = (b - a) / 2, (b + a) / 2
+    t0 = (a0 - c) / e
+
+    def T(k):
+        coef = np.zeros(k + 1)
+        coef[k] = 1.0
+        return npcheb.chebval(t0, coef)
+
+    got = C.filter_scalars(m, a, b, a0)
+    assert len(got) == m
+    for k, (alpha, cc, beta) in enumerate(got, start=1):
+        assert cc == c
+        assert alpha == pytest.approx(2 * T(k - 1) / (e * T(k)) if k > 1 else 1 / (e * t0), rel=1e-12)
+        assert beta == (0.0 if k == 1 else pytest.approx(T(k - 2) / T(k), rel=1e-12))

@@ -162,3 +162,22 @@ def test_offsets_order():
     off = G.offsets()
     assert off[0] == (0, -6) and off[5] == (0, -1) and off[6] == (0, 1) and off[11] == (0, 6)
     assert off[12] == (1, -6) and off[35] == (2, 6)
+
+
+@pytest.mark.parametrize("radius,h", [(1.0, 1.0), (2.0, 1.0), (3.0, 1.0), (3.5, 0.7), (4.2, 0.7)])
+def test_sphere_points_brute_force(radius, h):
+    # every integer triple with |(i, j, k)| h <= radius, found by plain loops
+    n_r, pts = G.sphere_points(radius, h)
+    m = int(radius / h) + 1
+    want = {(i, j, k) for i in range(-m, m + 1) for j in range(-m, m + 1) for k in range(-m, m + 1)
+            if (i * i + j * j + k * k) * h * h <= radius * radius * (1 + 1e-12)}
+    assert n_r == int(math.floor(radius / h))
+    assert len(pts) == len(want) and set(map(tuple, pts.tolist())) == want
+
+
+def test_sphere_point_counts_are_sums_of_three_squares():
+    # points of norm <= n for n = 0..9: sums of r3(n) = 1, 6, 12, 8, 6, 24, 24, 0, 12, 30
+    r3 = [1, 6, 12, 8, 6, 24, 24, 0, 12, 30]
+    for n in range(10):
+        _, pts = G.sphere_points(math.sqrt(n), 1.0)
+        assert len(pts) == sum(r3[:n + 1])

@@ -3,6 +3,7 @@ addition theorem, the Poisson solver against the analytic potential of
 Gaussian charges, LDA potentials against numerical derivatives of the
 energy density, Anderson mixing on a linear fixed point, and a small SCF
 whose converged eigenvalues are those of its own final Hamiltonian."""
+import dataclasses
 import math
 
 import numpy as np
@@ -81,6 +82,47 @@ def test_lda_potential_is_derivative():
     assert np.all(S.lda(np.array([0.0, 1e-15, -1e-3]))[1] == 0.0)
 
 
+def test_lda_energy_derivative_on_both_branches():
+    # d eps / d r_s against central differences of eps, on each side of r_s = 1
+    rs = np.array([0.05, 0.3, 0.9, 0.999, 1.001, 1.5, 4.0, 20.0])
+    d = 1e-6 * rs
+    num = (S.lda_eps(rs + d) - S.lda_eps(rs - d)) / (2 * d)
+    assert np.allclose(S.lda_deps_drs(rs), num, rtol=1e-7)
+
+
+def test_conjugate_gradient_matches_dense_solve():
+    rng = np.random.default_rng(4)
+    n = 40
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    x, it = S.conjugate_gradient(lambda v: A @ v, b, np.zeros(n), rtol=1e-13)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-11 * np.abs(x).max())
+    assert 0 < it <= 2 * n
+    # a start at the solution needs no iteration
+    x2, it2 = S.conjugate_gradient(lambda v: A @ v, b, np.linalg.solve(A, b), rtol=1e-10)
+    assert it2 == 0
+
+
+def test_ghost_points_brute_force():
+    # each (inside point, stencil offset) whose target lies outside the sphere, by plain loops
+    g = G.build_grid(3.2, 0.8)
+    nbr = G.neighbour_table(g)
+    owner, k, pts = S.ghost_points(g, nbr)
+    thr = math.floor((g.radius / g.h) ** 2 + 1e-9)
+    want = []
+    for r, (i, j, l) in enumerate(g.ijk.tolist()):
+        for axis in range(3):
+            for s in list(range(-6, 0)) + list(range(1, 7)):
+                q = [i, j, l]
+                q[axis] += s
+                if q[0] ** 2 + q[1] ** 2 + q[2] ** 2 > thr:
+                    want.append((r, abs(s), q[0], q[1], q[2]))
+    got = [(int(o), int(kk), *np.rint(p / g.h).astype(int).tolist()) for o, kk, p in zip(owner, k, pts)]
+    assert sorted(got) == sorted(want)
+    assert np.allclose(pts / g.h, np.rint(pts / g.h), atol=1e-12)
+
+
 def test_anderson_solves_linear_fixed_point():
     rng = np.random.default_rng(1)
     n = 5
@@ -108,10 +150,13 @@ def test_sad_density_normalised():
     assert abs(g.h ** 3 * rho.sum() - 5) < 1e-12 and (rho > 0).all()
 
 
+_D = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
+H_POS = [[0, 0, 0], [_D, _D, _D], [_D, -_D, -_D], [-_D, _D, -_D], [-_D, -_D, _D]]
+
+
 @pytest.fixture(scope="module")
 def sih4_scf():
-    d = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
-    pos = np.array([[0, 0, 0], [d, d, d], [d, -d, -d], [-d, d, -d], [-d, -d, d]], float)
+    pos = np.array(H_POS)
     species = np.array([0, 1, 1, 1, 1], np.int32)
     g = G.build_grid(float(np.sqrt((pos ** 2).sum(1)).max()) + 5.0, 0.7)
     nbr = G.neighbour_table(g)
@@ -145,12 +190,52 @@ def test_scf_energy_stationary(sih4_scf):
     assert np.all(np.abs(e[late] - e[-1]) < 10 * sre[late] ** 2 + 1e-8)
 
 
+def test_harris_foulkes_equals_kohn_sham_at_self_consistency(sih4_scf):
+    """The Harris-Foulkes energy at the input density equals the Kohn-Sham
+    functional evaluated directly at the output density up to second order in
+    their difference: kinetic + local + nonlocal from the orbitals, Hartree as
+    half the Coulomb self-energy, LDA exchange-correlation, ion-ion."""
+    H, nbr, st, reps = sih4_scf
+    g = H.grid
+    h3 = g.h ** 3
+    n_occ = 4
+    e_ii = S.ion_energy(np.array(H_POS), OH.PseudoParams().charges(np.array([0, 1, 1, 1, 1], np.int32)))
+    rho_in = st.rho_in
+    vh_in, _ = S.hartree(g, H.lap, nbr, rho_in)
+    exc_in, vxc_in = S.lda(rho_in)
+    Hin = dataclasses.replace(H, veff=H.vloc + vh_in + vxc_in)
+    lam, V = np.linalg.eigh(Hin.dense())
+    psi = V[:, :n_occ] / math.sqrt(h3)              # normalised in h^3 sum psi^2 = 1
+    e_hf = S.harris_foulkes(g.h, lam, n_occ, rho_in, vh_in, exc_in, vxc_in, e_ii)
+    # direct functional at the output density
+    rho_out = 2.0 * (psi ** 2).sum(1)
+    Hext = dataclasses.replace(H, veff=H.vloc)
+    e_one = 2.0 * h3 * float((psi * Hext.apply(psi)).sum())
+    vh_out, _ = S.hartree(g, H.lap, nbr, rho_out)
+    exc_out, _ = S.lda(rho_out)
+    e_ks = e_one + 0.5 * h3 * float(rho_out @ vh_out) + h3 * float(rho_out @ exc_out) + e_ii
+    drho = math.sqrt(h3 * float(((rho_out - rho_in) ** 2).sum()))
+    assert drho < 1e-3
+    assert abs(e_hf - e_ks) < 1e-6
+    # far from self-consistency (the superposed atomic start) the two differ clearly
+    rho0 = S.sad_density(g, np.array(H_POS), np.array([0, 1, 1, 1, 1], np.int32), 8)
+    vh0, _ = S.hartree(g, H.lap, nbr, rho0)
+    exc0, vxc0 = S.lda(rho0)
+    lam0, V0 = np.linalg.eigh(dataclasses.replace(H, veff=H.vloc + vh0 + vxc0).dense())
+    psi0 = V0[:, :n_occ] / math.sqrt(h3)
+    r0 = 2.0 * (psi0 ** 2).sum(1)
+    vh0o, _ = S.hartree(g, H.lap, nbr, r0)
+    e_ks0 = (2.0 * h3 * float((psi0 * Hext.apply(psi0)).sum()) + 0.5 * h3 * float(r0 @ vh0o)
+             + h3 * float(r0 @ S.lda(r0)[0]) + e_ii)
+    e_hf0 = S.harris_foulkes(g.h, lam0, n_occ, rho0, vh0, exc0, vxc0, e_ii)
+    assert abs(e_hf0 - e_ks0) > 100 * abs(e_hf - e_ks)
+
+
 def test_resume_from_saved_state_is_bit_exact(tmp_path):
     """What an SCF carries between steps (rho_in, V_H warm start, X, filter
     bounds, step counter, Anderson history) saved to .npz and loaded into a
     fresh state reproduces the next step exactly."""
-    d = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
-    pos = np.array([[0, 0, 0], [d, d, d], [d, -d, -d], [-d, d, -d], [-d, -d, d]], float)
+    pos = np.array(H_POS)
     species = np.array([0, 1, 1, 1, 1], np.int32)
     g = G.build_grid(float(np.sqrt((pos ** 2).sum(1)).max()) + 5.0, 0.7)
     nbr = G.neighbour_table(g)
