@@ -123,7 +123,7 @@ static void run_filter(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nve
 static int filter_impl(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
                        double a0, void* work, int64_t ldw, void* stream, int force_kernel) {
     return guarded([&] {
-        CHF_REQUIRE(H, "chebyshev_filter: null handle");
+        CHF_REQUIRE(H, force_kernel ? "chf_filter_generic: null handle" : "chebyshev_filter: null handle");
         check_device(H);
         check_block(H, dtype, X, ldx, nvec, "chebyshev_filter X");
         check_block(H, dtype, work, ldw, nvec, "chebyshev_filter work");

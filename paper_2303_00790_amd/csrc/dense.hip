@@ -653,6 +653,7 @@ int chf_workspace_bytes(const chf_ham* H, int op, chf_dtype dtype, int nvec, int
 
 int chf_reserve(chf_ham* H, chf_ctx* ctx, int op, chf_dtype dtype, int nvec, int64_t ldw) {
     return guard([&] {
+        CHF_REQUIRE(H, "chf_reserve: null Hamiltonian");
         const WsNeed w = ws_need(H, op, dtype, nvec, ldw);
         if ((w.scratch || w.scratch2 || w.vec || w.red) && !ctx) fail(CHF_EINVAL, "chf_reserve: operation needs a context");
         if (w.kb) H->kb_coef.ensure(w.kb);

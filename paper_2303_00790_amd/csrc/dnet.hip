@@ -733,7 +733,8 @@ int dnet_forward(dnet* N, const float* x, int S, float* y, void* stream) {
 
 int dnet_backward(dnet* N, const float* dy, void* stream) {
     return dguard([&] {
-        if (!N || !dy || N->S == 0) fail(CHF_EINVAL, "dnet_backward: call dnet_forward first");
+        if (!N || !dy) fail(CHF_EINVAL, "dnet_backward: null argument");
+        if (N->S == 0) fail(CHF_EINVAL, "dnet_backward: call dnet_forward first");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int S = N->S, C = N->C;
         auto Y = [&](int i) { return N->act[i]->y.as<bf16>(); };

@@ -94,3 +94,34 @@ def test_density_net_plan_matches_architecture():
     _, tape = U.forward(p, np.zeros((1, S, S, S)), keep=True)
     ref = {name: z.shape[1] for name, _, z, _, _ in tape}
     assert edges == [ref[name] for name in B.LAYER_NAMES]
+
+
+# Calls that accept null handles by design: destroy calls are no-ops on null, the
+# timer switch and the allocation counter take no pointer, and chf_last_error reads.
+NULL_OK = {"chf_ctx_destroy", "ham_destroy", "chf_scf_destroy", "dnet_destroy", "chf_timer",
+           "chf_device_allocations", "chf_last_error"}
+
+
+def test_every_call_rejects_null_arguments_on_the_host():
+    """Every entry point validates its pointers before any device work: with
+    null pointers (and unit scalars) it returns CHF_EINVAL and leaves a message
+    that names the call.  Runs without a GPU, so a call that reached the
+    device first would fail here instead."""
+    import ctypes
+    lib = B.lib()
+    for name in B.declared_symbols():
+        if name in NULL_OK:
+            continue
+        f = getattr(lib, name)
+        args = []
+        for t in f.argtypes:
+            if t in (ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t):
+                args.append(t(1))
+            elif t in (ctypes.c_double, ctypes.c_float):
+                args.append(t(1.0))
+            else:
+                args.append(None)
+        rc = f(*args)
+        msg = lib.chf_last_error().decode()
+        assert B.STATUS.get(rc) == "CHF_EINVAL", (name, rc, msg)
+        assert msg.startswith(name), (name, msg)
