@@ -125,3 +125,13 @@ def test_every_call_rejects_null_arguments_on_the_host():
         msg = lib.chf_last_error().decode()
         assert B.STATUS.get(rc) == "CHF_EINVAL", (name, rc, msg)
         assert msg.startswith(name), (name, msg)
+
+
+def test_ion_energy_matches_oracle_on_the_host():
+    # the ion-ion energy is host code: a 3 nm cluster (1,005 atoms) against the oracle's pair sum
+    from oracle import scf as OS
+    from synth.workloads import MODEL_PP
+    c = make_cluster(15.0, 2)
+    got = B.ion_energy(c.pos, c.species, MODEL_PP)
+    want = OS.ion_energy(c.pos, np.where(c.species == 0, MODEL_PP.z_si, MODEL_PP.z_h).astype(float))
+    assert abs(got - want) < 1e-12 * abs(want)
