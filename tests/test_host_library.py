@@ -1,6 +1,7 @@
 """Host-side checks of the C-ABI library (no GPU): it loads, exports every
 symbol the header declares, and its host-built ordering, neighbour and
 projector tables equal the oracle's bit for bit."""
+import math
 import os
 import re
 
@@ -135,3 +136,51 @@ def test_ion_energy_matches_oracle_on_the_host():
     got = B.ion_energy(c.pos, c.species, MODEL_PP)
     want = OS.ion_energy(c.pos, np.where(c.species == 0, MODEL_PP.z_si, MODEL_PP.z_h).astype(float))
     assert abs(got - want) < 1e-12 * abs(want)
+
+
+@pytest.mark.parametrize("radius,h", [
+    (math.sqrt(50.0) * 0.7, 0.7),    # radius on a lattice shell: the 1e-9 tolerance decides membership
+    (math.sqrt(27.0) * 0.9, 0.9),
+    (12.0, 1.0), (16.0, 1.0),        # 4 and 5 blocks per edge: Hilbert order 2 then 3
+    (28.0, 1.0), (32.0, 1.0),        # 8 and 9 blocks per edge: order 3 then 4
+    (1.0001, 1.0),                   # the smallest grid: the centre and its 6 neighbours
+])
+def test_ordering_edge_radii(radius, h):
+    ijk, rows, nbr, n_rows = B.ordering_host(h, radius, G.ORDER_HILBERT)
+    g = G.build_grid(radius, h)
+    assert np.array_equal(ijk, g.ijk) and np.array_equal(rows, g.row_of_rank) and n_rows == g.n_rows
+    assert np.array_equal(nbr, G.neighbour_table(g))
+    if radius < 2 * h:
+        # the centre sees all six; each outer point sees the centre and the opposite point on its axis
+        assert len(ijk) == 7 and (nbr >= 0).sum() == 6 + 6 * 2
+
+
+def _projector_parity(h, radius, pos, species, pp):
+    off, rank, beta = B.projectors_host(h, radius, pos, species, pp)
+    g = G.build_grid(radius, h)
+    Bm, _ = OH.projector_matrix(g, pos, species, pp)
+    Bm = Bm.tocsc()
+    assert len(off) == Bm.shape[1] // 4 + 1 and off[-1] == len(rank)
+    for a in range(len(off) - 1):
+        rows_o = np.unique(Bm[:, 4 * a:4 * a + 4].tocoo().row)
+        assert np.array_equal(rank[off[a]:off[a + 1]], rows_o)
+        assert np.allclose(beta[off[a]:off[a + 1]], Bm[rows_o, 4 * a:4 * a + 4].toarray(), rtol=1e-14, atol=1e-17)
+    return off, rank, beta
+
+
+def test_projector_tables_edge_cases():
+    pp = OH.PseudoParams()
+    radius, h = 9.0, 0.7
+    # a Si on a grid point (the p channels vanish there), one whose support the sphere cuts,
+    # one wholly outside the support of the others, and an H (no projectors)
+    pos = np.array([[0.0, 0.0, 0.0], [7.7, 0.3, -0.2], [-3.1, 4.4, 2.0], [0.0, 0.0, 1.5]])
+    species = np.array([0, 0, 0, 1], np.int32)
+    off, rank, beta = _projector_parity(h, radius, pos, species, pp)
+    assert len(off) == 4
+    full = off[1] - off[0]
+    assert off[2] - off[1] < full          # the cut atom keeps fewer support points
+    # H only, and no atoms at all: no projector entries
+    off, rank, _ = _projector_parity(h, radius, pos[3:], species[3:], pp)
+    assert list(off) == [0] and len(rank) == 0
+    off, rank, _ = _projector_parity(h, radius, np.zeros((0, 3)), np.zeros(0, np.int32), pp)
+    assert list(off) == [0] and len(rank) == 0
