@@ -30,3 +30,16 @@ def test_module_helpers():
     import bench
     assert len(bench.kernel_source_hash()) == 64
     assert "logical CPUs" in bench.host_cpu()
+
+
+def test_committed_traffic_record_is_consistent():
+    """profiles/traffic.json: the bytes per launch are the two counters times
+    their copy-kernel scales, and the write counter is exactly one store of
+    Y_{k+1} over the padded rows (16 nm: 53,417,472 rows x 256 FP32 vectors)."""
+    import json
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["d16nm:f32:256"]
+    total = rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
+    assert abs(total - rec["bytes_per_launch"]) < 1e-6 * total
+    assert rec["write_kib"] * 1024 == 53_417_472 * 256 * 4
+    assert 1.9 < rec["fetch_scale"] < 2.1 and rec["write_scale"] == 1.0
+    assert len(rec["source_sha256"]) == 64
