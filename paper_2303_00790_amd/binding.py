@@ -174,6 +174,11 @@ def _ptr(t) -> P:
     return P(t.data_ptr())
 
 
+def _torch_f64():
+    import torch
+    return torch.float64
+
+
 def _dtype_code(t) -> int:
     import torch
     if t.dtype == torch.float64:
@@ -183,10 +188,39 @@ def _dtype_code(t) -> int:
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
-def _block(t):
+def _on_gpu(t, what: str) -> None:
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: expected a tensor in GPU memory")
+
+
+def _block(t, rows: int | None = None, like=None, nvec: int | None = None, what: str = "vector block"):
+    """(pointer, ld) of a row-major block.  The library sees only the pointer and
+    ld, so the extent it will touch is checked here: at least `rows` rows, at
+    least `nvec` columns, the dtype of `like`, device memory."""
     if t.dim() != 2 or t.stride(1) != 1:
         raise ValueError("vector blocks must be 2-D with contiguous rows")
+    if rows is not None and t.shape[0] < rows:
+        raise ValueError(f"{what}: {t.shape[0]} rows, the Hamiltonian has {rows}")
+    if nvec is not None and not 1 <= nvec <= t.shape[1]:
+        raise ValueError(f"{what}: nvec {nvec} outside 1..{t.shape[1]}")
+    if like is not None and t.dtype != like.dtype:
+        raise TypeError(f"{what}: dtype {t.dtype} differs from {like.dtype}")
+    _on_gpu(t, what)
     return _ptr(t), t.stride(0)
+
+
+def _vec(t, n: int, what: str, double: bool = True):
+    """Pointer to a contiguous device vector of at least n FP64 (or FP32) values."""
+    import torch
+    want = torch.float64 if double else torch.float32
+    if t.dtype != want:
+        raise TypeError(f"{what}: dtype {t.dtype}, expected {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} values, needs {n}")
+    _on_gpu(t, what)
+    return _ptr(t)
 
 
 def make_pp(pp) -> PP:
@@ -297,39 +331,41 @@ class Hamiltonian:
         return out
 
     def set_veff(self, veff):
-        call("ham_set_veff", self.handle, _ptr(veff.contiguous()), _stream())
+        call("ham_set_veff", self.handle, _vec(veff.contiguous(), self.n_rows, "veff"), _stream())
 
     def apply(self, X, Y, generic: bool = False):
-        px, ldx = _block(X)
-        py, ldy = _block(Y)
+        px, ldx = _block(X, self.n_rows, what="X")
+        py, ldy = _block(Y, self.n_rows, like=X, nvec=X.shape[1], what="Y")
         call("chf_ham_apply_generic" if generic else "ham_apply", self.handle, _dtype_code(X), px, ldx, py, ldy,
              X.shape[1], _stream())
 
     def filter(self, X, work, degree: int, a: float, b: float, a0: float, generic: bool = False, nvec=None):
-        px, ldx = _block(X)
-        pw, ldw = _block(work)
+        px, ldx = _block(X, self.n_rows, nvec=nvec or X.shape[1], what="X")
+        pw, ldw = _block(work, self.n_rows, like=X, nvec=nvec or X.shape[1], what="work")
         call("chf_filter_generic" if generic else "chebyshev_filter", self.handle, _dtype_code(X), px, ldx,
              nvec or X.shape[1], degree, a, b, a0, pw, ldw, _stream())
 
     def lanczos_bound(self, ctx: Context, v0, k: int = 10):
         out = (C.c_double * 3)()
-        call("lanczos_bound", self.handle, ctx.handle, _ptr(v0), k, C.cast(out, P), _stream())
+        call("lanczos_bound", self.handle, ctx.handle, _vec(v0, self.n_rows, "v0"), k, C.cast(out, P), _stream())
         return tuple(out)
 
     def density(self, X, n_occ: int, rho):
-        px, ldx = _block(X)
-        call("chf_density", self.handle, _dtype_code(X), px, ldx, n_occ, _ptr(rho), _stream())
+        px, ldx = _block(X, self.n_rows, nvec=n_occ, what="X")
+        call("chf_density", self.handle, _dtype_code(X), px, ldx, n_occ, _vec(rho, self.n_rows, "rho"), _stream())
 
     def hartree(self, ctx: Context, rho, vh, rtol: float = 1e-12, max_iter: int = 20000) -> int:
         it = C.c_int()
-        call("chf_hartree", self.handle, ctx.handle, _ptr(rho), _ptr(vh), rtol, max_iter, C.byref(it), _stream())
+        call("chf_hartree", self.handle, ctx.handle, _vec(rho, self.n_rows, "rho"), _vec(vh, self.n_rows, "vh"), rtol,
+             max_iter, C.byref(it), _stream())
         return it.value
 
     def lda(self, rho, exc, vxc):
-        call("chf_lda", self.handle, _ptr(rho), _ptr(exc) if exc is not None else None, _ptr(vxc), _stream())
+        call("chf_lda", self.handle, _vec(rho, self.n_rows, "rho"),
+             _vec(exc, self.n_rows, "exc") if exc is not None else None, _vec(vxc, self.n_rows, "vxc"), _stream())
 
     def density_fix(self, rho, n_electrons: int):
-        call("chf_density_fix", self.handle, _ptr(rho), n_electrons, _stream())
+        call("chf_density_fix", self.handle, _vec(rho, self.n_rows, "rho"), n_electrons, _stream())
 
     def sad_density(self, pos, species, n_electrons: int, alpha_si: float = 0.074, alpha_h: float = 0.21):
         import torch
@@ -348,23 +384,25 @@ def ion_energy(pos, species, pp) -> float:
 
 
 def gram(ctx: Context, A, B, S) -> None:
-    pa, lda = _block(A)
-    pb, ldb = _block(B)
-    ps, lds = _block(S)
+    pa, lda = _block(A, what="A")
+    pb, ldb = _block(B, A.shape[0], like=A, what="B")
+    ps, lds = _block(S, A.shape[1], nvec=B.shape[1], what="S")
+    if S.dtype != _torch_f64():
+        raise TypeError("S: must be FP64")
     call("gram", ctx.handle, _dtype_code(A), pa, lda, pb, ldb, A.shape[0], A.shape[1], B.shape[1], ps, lds, _stream())
 
 
 def orthonormalize(ctx: Context, X, nvec=None) -> int:
-    px, ldx = _block(X)
+    px, ldx = _block(X, nvec=nvec or X.shape[1], what="X")
     fb = C.c_int()
     call("orthonormalize", ctx.handle, _dtype_code(X), px, ldx, X.shape[0], nvec or X.shape[1], C.byref(fb), _stream())
     return fb.value
 
 
 def rayleigh_ritz(H: Hamiltonian, ctx: Context, X, work, nvec=None) -> np.ndarray:
-    px, ldx = _block(X)
-    pw, ldw = _block(work)
     n = nvec or X.shape[1]
+    px, ldx = _block(X, H.n_rows, nvec=n, what="X")
+    pw, ldw = _block(work, H.n_rows, like=X, what="work")
     eig = np.zeros(n, np.float64)
     call("rayleigh_ritz", H.handle, ctx.handle, _dtype_code(X), px, ldx, n, P(eig.ctypes.data), pw, ldw, _stream())
     return eig
@@ -394,13 +432,17 @@ class Scf:
     def __init__(self, H: Hamiltonian, ctx: Context, params: ScfParams, rho0, v_lanczos):
         self.handle = P()
         self._keep = (H, ctx)
-        call("chf_scf_create", H.handle, ctx.handle, C.byref(params), _ptr(rho0), _ptr(v_lanczos),
-             C.byref(self.handle))
+        call("chf_scf_create", H.handle, ctx.handle, C.byref(params), _vec(rho0, H.n_rows, "rho0"),
+             _vec(v_lanczos, H.n_rows, "v_lanczos"), C.byref(self.handle))
         self.nvec = params.nvec
+        self.n_rows = H.n_rows
+        self.filter_double = params.filter_dtype == CHF_F64
 
     def step(self, X, work):
-        px, ldx = _block(X)
-        pw, ldw = _block(work)
+        if (X.dtype == _torch_f64()) != self.filter_double:
+            raise TypeError(f"X: dtype {X.dtype} is not the SCF's filter precision")
+        px, ldx = _block(X, self.n_rows, nvec=self.nvec, what="X")
+        pw, ldw = _block(work, self.n_rows, like=X, nvec=self.nvec, what="work")
         rep = ScfReport()
         eig = np.zeros(self.nvec, np.float64)
         call("scf_step", self.handle, px, ldx, pw, ldw, C.byref(rep), P(eig.ctypes.data))
@@ -419,8 +461,8 @@ class Scf:
         call("chf_scf_load", self.handle, P(state.ctypes.data), int(state.size))
 
     def fields(self, rho_in, vh=None):
-        call("chf_scf_get_fields", self.handle, _ptr(rho_in) if rho_in is not None else None,
-             _ptr(vh) if vh is not None else None)
+        call("chf_scf_get_fields", self.handle, _vec(rho_in, self.n_rows, "rho_in") if rho_in is not None else None,
+             _vec(vh, self.n_rows, "vh") if vh is not None else None)
 
     def close(self):
         if self.handle:

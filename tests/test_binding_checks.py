@@ -1,0 +1,133 @@
+"""The Python binding's argument checks, on the CPU.
+
+The library receives only pointers and leading dimensions, so the binding
+checks the extent each call will touch (rows of the Hamiltonian, vector
+count, FP64 vector lengths), matching dtypes and device memory before it
+calls.  Here the C call, the stream lookup and the device check are replaced
+by stand-ins: the shapes the GPU tests use must pass, and every malformed
+argument must raise before anything reaches the library."""
+import types
+
+import pytest
+import torch
+
+B = pytest.importorskip("paper_2303_00790_amd.binding")
+
+N_ROWS = 1024
+
+
+@pytest.fixture
+def fake(monkeypatch):
+    calls = []
+    monkeypatch.setattr(B, "call", lambda name, *args: calls.append(name))
+    monkeypatch.setattr(B, "_on_gpu", lambda t, what: None)
+    monkeypatch.setattr(B, "_stream", lambda: None)
+    H = B.Hamiltonian.__new__(B.Hamiltonian)
+    H.handle = None
+    H.n_rows, H.n_points = N_ROWS, 900
+    ctx = types.SimpleNamespace(handle=None)
+    return H, ctx, calls
+
+
+def blk(rows=N_ROWS, cols=8, dtype=torch.float64):
+    return torch.zeros((rows, cols), dtype=dtype)
+
+
+def vec(n=N_ROWS, dtype=torch.float64):
+    return torch.zeros(n, dtype=dtype)
+
+
+def test_shapes_the_device_tests_use_are_accepted(fake):
+    H, ctx, calls = fake
+    X = blk(cols=40)
+    H.apply(X, torch.empty_like(X))
+    H.apply(X[:, :36], torch.full_like(X, 0.0)[:, :36])      # column views with ld > nvec
+    H.filter(X, torch.zeros_like(X), 3, 0.0, 1.0, -1.0)
+    H.filter(X, torch.zeros_like(X), 3, 0.0, 1.0, -1.0, nvec=33)
+    H.density(X, 33, vec())
+    H.hartree(ctx, vec(), vec())
+    H.lda(vec(), vec(), vec())
+    H.lda(vec(), None, vec())
+    H.density_fix(vec(), 8)
+    H.lanczos_bound(ctx, vec())
+    H.set_veff(vec())
+    B.gram(ctx, blk(5003, 70), blk(5003, 45), blk(70, 45))
+    B.gram(ctx, blk(300, 17, torch.float32), blk(300, 17, torch.float32), blk(17, 17))
+    B.orthonormalize(ctx, X)
+    B.rayleigh_ritz(H, ctx, X, torch.zeros_like(X))
+    assert calls.count("ham_apply") == 2 and "rayleigh_ritz" in calls and "gram" in calls
+
+
+@pytest.mark.parametrize("case,err", [
+    ("X rows short", ValueError),
+    ("Y rows short", ValueError),
+    ("Y dtype differs", TypeError),
+    ("Y narrower than X", ValueError),
+    ("X not 2-D", ValueError),
+    ("X columns strided", ValueError),
+    ("filter nvec too large", ValueError),
+    ("filter work dtype differs", TypeError),
+    ("density n_occ too large", ValueError),
+    ("rho short", ValueError),
+    ("rho FP32", TypeError),
+    ("rho strided", ValueError),
+    ("veff short", ValueError),
+    ("v0 short", ValueError),
+    ("gram B rows short", ValueError),
+    ("gram S too small", ValueError),
+    ("gram S FP32", TypeError),
+    ("gram B dtype differs", TypeError),
+    ("rayleigh-ritz work rows short", ValueError),
+])
+def test_malformed_arguments_raise_before_the_call(fake, case, err):
+    H, ctx, calls = fake
+    X = blk()
+    run = {
+        "X rows short": lambda: H.apply(blk(N_ROWS - 1), blk()),
+        "Y rows short": lambda: H.apply(X, blk(N_ROWS - 1)),
+        "Y dtype differs": lambda: H.apply(X, blk(dtype=torch.float32)),
+        "Y narrower than X": lambda: H.apply(X, blk(cols=4)),
+        "X not 2-D": lambda: H.apply(vec(), vec()),
+        "X columns strided": lambda: H.apply(blk(cols=16)[:, ::2], blk()),
+        "filter nvec too large": lambda: H.filter(X, blk(), 3, 0.0, 1.0, -1.0, nvec=9),
+        "filter work dtype differs": lambda: H.filter(X, blk(dtype=torch.float32), 3, 0.0, 1.0, -1.0),
+        "density n_occ too large": lambda: H.density(X, 9, vec()),
+        "rho short": lambda: H.hartree(ctx, vec(N_ROWS - 1), vec()),
+        "rho FP32": lambda: H.lda(vec(dtype=torch.float32), None, vec()),
+        "rho strided": lambda: H.density_fix(vec(2 * N_ROWS)[::2], 8),
+        "veff short": lambda: H.set_veff(vec(N_ROWS - 1)),
+        "v0 short": lambda: H.lanczos_bound(ctx, vec(10)),
+        "gram B rows short": lambda: B.gram(ctx, blk(100, 4), blk(99, 4), blk(4, 4)),
+        "gram S too small": lambda: B.gram(ctx, blk(100, 4), blk(100, 5), blk(4, 4)),
+        "gram S FP32": lambda: B.gram(ctx, blk(100, 4), blk(100, 4), blk(4, 4, torch.float32)),
+        "gram B dtype differs": lambda: B.gram(ctx, blk(100, 4), blk(100, 4, torch.float32), blk(4, 4)),
+        "rayleigh-ritz work rows short": lambda: B.rayleigh_ritz(H, ctx, X, blk(N_ROWS - 1)),
+    }[case]
+    with pytest.raises(err):
+        run()
+    assert calls == []
+
+
+def test_scf_step_checks_precision_and_extent(fake):
+    H, ctx, calls = fake
+    scf = B.Scf.__new__(B.Scf)
+    scf.handle = None
+    scf.nvec, scf.n_rows, scf.filter_double = 8, N_ROWS, False
+    scf.step(blk(dtype=torch.float32), blk(dtype=torch.float32))
+    assert calls == ["scf_step"]
+    with pytest.raises(TypeError):
+        scf.step(blk(), blk())                                   # FP64 block for an FP32 filter
+    with pytest.raises(ValueError):
+        scf.step(blk(cols=7, dtype=torch.float32), blk(dtype=torch.float32))
+    with pytest.raises(TypeError):
+        scf.step(blk(dtype=torch.float32), blk())
+    assert calls == ["scf_step"]
+
+
+def test_host_tensors_are_refused(monkeypatch):
+    # the real device check: a tensor in host memory never reaches the library
+    monkeypatch.setattr(B, "call", lambda name, *args: pytest.fail("reached the library"))
+    with pytest.raises(ValueError, match="GPU memory"):
+        B._block(blk())
+    with pytest.raises(ValueError, match="GPU memory"):
+        B._vec(vec(), N_ROWS, "rho")
