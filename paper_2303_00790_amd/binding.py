@@ -514,6 +514,8 @@ class DensityNet:
 
     def set_params(self, flat: np.ndarray) -> None:
         flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.size != self.n_params:
+            raise ValueError(f"set_params: {flat.size} values, the network has {self.n_params}")
         call("dnet_set_params", self.handle, P(flat.ctypes.data))
 
     def get_grads(self) -> np.ndarray:
@@ -522,18 +524,24 @@ class DensityNet:
         return out
 
     def forward(self, x, y):
-        call("dnet_forward", self.handle, _ptr(x), int(round(x.numel() ** (1 / 3))), _ptr(y), _stream())
+        S = int(round(x.numel() ** (1 / 3)))
+        if S ** 3 != x.numel():
+            raise ValueError(f"forward: x holds {x.numel()} values, not an S^3 patch")
+        call("dnet_forward", self.handle, _vec(x, S ** 3, "x", double=False), S, _vec(y, S ** 3, "y", double=False),
+             _stream())
+        self._n_out = S ** 3
 
     def backward(self, dy):
-        call("dnet_backward", self.handle, _ptr(dy), _stream())
+        call("dnet_backward", self.handle, _vec(dy, getattr(self, "_n_out", 0), "dy", double=False), _stream())
 
     def adam(self, lr: float, step: int):
         call("dnet_adam", self.handle, lr, step, _stream())
 
     def mse(self, y, t, dy=None) -> float:
         loss = C.c_double()
-        call("dnet_mse", self.handle, _ptr(y), _ptr(t), y.numel(), C.byref(loss), _ptr(dy) if dy is not None else None,
-             _stream())
+        n = y.numel()
+        call("dnet_mse", self.handle, _vec(y, n, "y", double=False), _vec(t, n, "t", double=False), n, C.byref(loss),
+             _vec(dy, n, "dy", double=False) if dy is not None else None, _stream())
         return loss.value
 
 
@@ -544,17 +552,20 @@ def dnet_plan(S: int) -> list[int]:
 
 
 def crop(box, D: int, S: int, origin, sym: int, patch) -> None:
-    call("dnet_crop", _ptr(box), D, S, int(origin[0]), int(origin[1]), int(origin[2]), sym, _ptr(patch), _stream())
+    call("dnet_crop", _vec(box, D ** 3, "box", double=False), D, S, int(origin[0]), int(origin[1]), int(origin[2]), sym,
+         _vec(patch, S ** 3, "patch", double=False), _stream())
 
 
 def highpass(box, D: int, sigma: float, out, work) -> None:
-    call("dnet_highpass", _ptr(box), D, float(sigma), _ptr(out), _ptr(work), _stream())
+    call("dnet_highpass", _vec(box, D ** 3, "box", double=False), D, float(sigma),
+         _vec(out, D ** 3, "out", double=False), _vec(work, 2 * D ** 3, "work", double=False), _stream())
 
 
 def rows_to_box(H: "Hamiltonian", rows, scale: float, box, D: int, off: int) -> None:
-    call("chf_rows_to_box", H.handle, _ptr(rows), scale, _ptr(box), D, off, _stream())
+    call("chf_rows_to_box", H.handle, _vec(rows, H.n_rows, "rows"), scale, _vec(box, D ** 3, "box", double=False), D,
+         off, _stream())
 
 
 def box_to_rows(H: "Hamiltonian", box, D: int, off: int, scale: float, base, out) -> None:
-    call("chf_box_to_rows", H.handle, _ptr(box), D, off, scale, _ptr(base) if base is not None else None, _ptr(out),
-         _stream())
+    call("chf_box_to_rows", H.handle, _vec(box, D ** 3, "box", double=False), D, off, scale,
+         _vec(base, H.n_rows, "base") if base is not None else None, _vec(out, H.n_rows, "out"), _stream())

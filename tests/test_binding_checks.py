@@ -131,3 +131,61 @@ def test_host_tensors_are_refused(monkeypatch):
         B._block(blk())
     with pytest.raises(ValueError, match="GPU memory"):
         B._vec(vec(), N_ROWS, "rho")
+
+
+@pytest.fixture
+def fake_net(fake):
+    calls = fake[2]            # the stand-ins of `fake` record these calls too
+    net = B.DensityNet.__new__(B.DensityNet)
+    net.handle = None
+    net.n_params = 100
+    return net, calls
+
+
+def f32(n):
+    return torch.zeros(n, dtype=torch.float32)
+
+
+def test_density_net_shapes_accepted(fake_net, fake):
+    net, calls = fake_net
+    H = fake[0]
+    S, D = 16, 24
+    import numpy as np
+    net.set_params(np.zeros(100, np.float32))
+    x = torch.zeros((S, S, S), dtype=torch.float32)
+    net.forward(x, torch.zeros_like(x))
+    net.mse(x, torch.zeros_like(x), torch.zeros_like(x))
+    net.backward(torch.zeros_like(x))
+    B.crop(f32(D ** 3), D, S, (1, 2, 3), 5, f32(S ** 3))
+    B.highpass(f32(D ** 3), D, 8.0, f32(D ** 3), f32(2 * D ** 3))
+    B.rows_to_box(H, vec(), 30.0, f32(D ** 3), D, 3)
+    B.box_to_rows(H, f32(D ** 3), D, 3, 30.0, None, vec())
+    B.box_to_rows(H, f32(D ** 3), D, 3, 30.0, vec(), vec())
+    assert calls[:4] == ["dnet_set_params", "dnet_forward", "dnet_mse", "dnet_backward"]
+
+
+@pytest.mark.parametrize("case", ["params short", "x not a cube", "y short", "dy short", "t short", "crop box short",
+                                  "crop patch short", "highpass work short", "rows_to_box rows short",
+                                  "box_to_rows box short", "box_to_rows out FP32"])
+def test_density_net_malformed_arguments_raise(fake_net, fake, case):
+    import numpy as np
+    net, calls = fake_net
+    H = fake[0]
+    S, D = 16, 24
+    net._n_out = S ** 3
+    run = {
+        "params short": lambda: net.set_params(np.zeros(99, np.float32)),
+        "x not a cube": lambda: net.forward(f32(S ** 3 + 1), f32(S ** 3 + 1)),
+        "y short": lambda: net.forward(f32(S ** 3), f32(S ** 3 - 1)),
+        "dy short": lambda: net.backward(f32(S ** 3 - 1)),
+        "t short": lambda: net.mse(f32(S ** 3), f32(S ** 3 - 1)),
+        "crop box short": lambda: B.crop(f32(D ** 3 - 1), D, S, (0, 0, 0), 0, f32(S ** 3)),
+        "crop patch short": lambda: B.crop(f32(D ** 3), D, S, (0, 0, 0), 0, f32(S ** 3 - 1)),
+        "highpass work short": lambda: B.highpass(f32(D ** 3), D, 8.0, f32(D ** 3), f32(D ** 3)),
+        "rows_to_box rows short": lambda: B.rows_to_box(H, vec(N_ROWS - 1), 1.0, f32(D ** 3), D, 0),
+        "box_to_rows box short": lambda: B.box_to_rows(H, f32(D ** 3 - 1), D, 0, 1.0, None, vec()),
+        "box_to_rows out FP32": lambda: B.box_to_rows(H, f32(D ** 3), D, 0, 1.0, None, vec(dtype=torch.float32)),
+    }[case]
+    with pytest.raises((ValueError, TypeError)):
+        run()
+    assert calls == []
