@@ -189,3 +189,15 @@ def test_density_net_malformed_arguments_raise(fake_net, fake, case):
     with pytest.raises((ValueError, TypeError)):
         run()
     assert calls == []
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback: without the built library every call raises
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libchfsi.so"))
+    monkeypatch.setattr(B, "_stream", lambda: None)     # this host has no GPU to ask for a stream
+    with pytest.raises(RuntimeError, match="not built"):
+        B.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        B.Hamiltonian(torch.zeros((1, 3), dtype=torch.float64).numpy(), [0], types.SimpleNamespace(
+            z_si=4.0, z_h=1.0, r_loc=0.7, r_loc_h=0.5, r_c=1.2, r_cut=4.8, h_s=3.0, h_p=0.0), 0.7, 5.0)
