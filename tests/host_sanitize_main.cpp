@@ -1,8 +1,9 @@
 // Host-side table construction (grid and blockwise Hilbert ordering, row
 // neighbour table, projector supports, per-row entries, block atom lists)
-// run under AddressSanitizer and UndefinedBehaviorSanitizer, with a few
-// consistency checks.  Built and run by tests/test_host_sanitizers.py with the
+// run under AddressSanitizer and UndefinedBehaviorSanitizer, with consistency
+// checks between the gather-side and scatter-side projector tables.  Built and run by tests/test_host_sanitizers.py with the
 // host compiler only; nothing here touches a GPU.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -68,14 +69,44 @@ static int run(double h, double radius, int ordering, int n_atoms, uint64_t seed
     EXPECT(P.ent_off.back() == int64_t(P.sup_row.size()));
     for (int64_t r = 0; r < g.n_rows; ++r) EXPECT(P.ent_off[size_t(r)] <= P.ent_off[size_t(r) + 1]);
     for (size_t j = 0; j < P.sup_row.size(); ++j) EXPECT(P.sup_row[j] >= 0 && P.sup_row[j] < g.n_rows);
+    // the per-row entries are the transpose of the per-atom supports: walking the
+    // atoms in order and appending each support pair to its row reproduces every
+    // row's entry list (atoms ascending) with the same projector values, bit for bit
+    {
+        std::vector<int64_t> fill(P.ent_off.begin(), P.ent_off.end() - 1);
+        for (int64_t a = 0; a < P.n_proj; ++a) {
+            for (int64_t j = P.sup_off[size_t(a)]; j < P.sup_off[size_t(a) + 1]; ++j) {
+                if (j > P.sup_off[size_t(a)]) EXPECT(P.sup_row[size_t(j)] > P.sup_row[size_t(j - 1)]);
+                const int64_t e = fill[size_t(P.sup_row[size_t(j)])]++;
+                EXPECT(e < P.ent_off[size_t(P.sup_row[size_t(j)]) + 1]);
+                EXPECT(P.ent_atom[size_t(e)] == a);
+                for (int m = 0; m < 4; ++m) EXPECT(P.ent_beta[size_t(4 * e + m)] == P.sup_beta[size_t(4 * j + m)]);
+            }
+        }
+        for (int64_t r = 0; r < g.n_rows; ++r) EXPECT(fill[size_t(r)] == P.ent_off[size_t(r) + 1]);
+    }
     if (ordering == CHF_ORDER_HILBERT) {
         build_block_atoms(g, P);
         EXPECT(int64_t(P.blk_atom_off.size()) == g.n_blocks + 1);
+        int max_na = 0;
         for (int64_t b = 0; b < g.n_blocks; ++b) {
             const int64_t e0 = P.ent_off[size_t(b * kBlockPts)], e1 = P.ent_off[size_t((b + 1) * kBlockPts)];
-            const int64_t na = P.blk_atom_off[size_t(b) + 1] - P.blk_atom_off[size_t(b)];
-            for (int64_t e = e0; e < e1; ++e) EXPECT(P.ent_slot[size_t(e)] < na || na > 255);
+            const int64_t a0 = P.blk_atom_off[size_t(b)], na = P.blk_atom_off[size_t(b) + 1] - a0;
+            max_na = std::max(max_na, int(na));
+            // the block's list holds exactly the atoms with an entry in its rows, ascending
+            std::vector<int32_t> seen;
+            for (int64_t e = e0; e < e1; ++e) seen.push_back(P.ent_atom[size_t(e)]);
+            std::sort(seen.begin(), seen.end());
+            seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+            EXPECT(int64_t(seen.size()) == na);
+            for (int64_t i = 0; i < na; ++i) EXPECT(P.blk_atoms[size_t(a0 + i)] == seen[size_t(i)]);
+            // and every entry's slot names its own atom in that list
+            for (int64_t e = e0; e < e1; ++e) {
+                EXPECT(P.ent_slot[size_t(e)] < na || na > 255);
+                if (na <= 255) EXPECT(P.blk_atoms[size_t(a0 + P.ent_slot[size_t(e)])] == P.ent_atom[size_t(e)]);
+            }
         }
+        EXPECT(P.max_block_atoms == max_na);
     }
     std::printf("h %.2f radius %.1f ordering %d: %lld points, %lld rows, %zu support entries\n", h, radius, ordering,
                 (long long)g.n, (long long)g.n_rows, P.sup_row.size());
