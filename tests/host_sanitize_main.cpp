@@ -1,8 +1,9 @@
 // Host-side table construction (grid and blockwise Hilbert ordering, row
 // neighbour table, projector supports, per-row entries, block atom lists)
 // run under AddressSanitizer and UndefinedBehaviorSanitizer, with consistency
-// checks between the gather-side and scatter-side projector tables.  Built and run by tests/test_host_sanitizers.py with the
-// host compiler only; nothing here touches a GPU.
+// checks between the gather-side and scatter-side projector tables.  Built and
+// run by tests/test_host_sanitizers.py with the host compiler only; nothing
+// here touches a GPU.
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
