@@ -49,6 +49,38 @@ static int run(double h, double radius, int ordering, int n_atoms, uint64_t seed
     EXPECT(int64_t(nbr.size()) == g.n_rows * 36);
     for (int64_t r = 0; r < g.n_rows; ++r)
         for (int k = 0; k < 36; ++k) EXPECT(nbr[size_t(r * 36 + k)] >= -1 && nbr[size_t(r * 36 + k)] < g.n_rows);
+    for (int64_t r = 0; r < g.n_rows; ++r)        // padding rows have no neighbours
+        if (g.rank_of_row[size_t(r)] < 0)
+            for (int k = 0; k < 36; ++k) EXPECT(nbr[size_t(r * 36 + k)] == -1);
+    if (ordering == CHF_ORDER_HILBERT) {
+        for (int64_t q = 0; q < g.n; ++q) {
+            const int i = g.ijk[size_t(3 * q)], j = g.ijk[size_t(3 * q + 1)], k = g.ijk[size_t(3 * q + 2)];
+            const int64_t row = g.row_of_rank[size_t(q)], s = row / kBlockPts;
+            // the point's block coordinates, and its bit in the block's inside mask
+            EXPECT(g.blocks[size_t(3 * s)] == (i + g.n_r) / kBlock);
+            EXPECT(g.blocks[size_t(3 * s + 1)] == (j + g.n_r) / kBlock);
+            EXPECT(g.blocks[size_t(3 * s + 2)] == (k + g.n_r) / kBlock);
+            const int l = int(row % kBlockPts);
+            EXPECT((g.block_mask[size_t(s * 8 + l / 64)] >> (l % 64)) & 1);
+            // every stencil offset that leaves the block through a face lands, when
+            // inside the sphere, in the block the face table names
+            for (int axis = 0; axis < 3; ++axis)
+                for (int d = -6; d <= 6; ++d) {
+                    if (d == 0) continue;
+                    int c[3] = {i, j, k};
+                    c[axis] += d;
+                    const int64_t nr_ = g.row_of(c[0], c[1], c[2]);
+                    const int64_t ns = nr_ < 0 ? -1 : nr_ / kBlockPts;
+                    if (ns < 0 || ns == s) continue;
+                    const int f = 2 * axis + (d > 0 ? 1 : 0);
+                    EXPECT(g.block_nbr[size_t(6 * s + f)] == ns);
+                }
+        }
+        for (int64_t s = 0; s < g.n_blocks; ++s)      // mask bits are exactly the inside rows
+            for (int l = 0; l < kBlockPts; ++l)
+                EXPECT((((g.block_mask[size_t(s * 8 + l / 64)] >> (l % 64)) & 1) != 0) ==
+                       (g.rank_of_row[size_t(s * kBlockPts + l)] >= 0));
+    }
     // atoms inside the sphere, two thirds Si
     std::vector<double> pos(size_t(3 * n_atoms));
     std::vector<int> species(static_cast<size_t>(n_atoms), 0);

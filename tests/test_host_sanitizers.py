@@ -5,7 +5,9 @@ supports, per-row KB entries and block atom lists are built by host C++
 (paper_2303_00790_amd/csrc/host_grid.cpp).  tests/host_sanitize_main.cpp
 drives them on small clusters (both orderings, three spacings) with the host
 compiler's address and undefined-behaviour sanitizers and checks their
-invariants: the per-row projector entries are the exact transpose of the
+invariants: every stencil offset that leaves a block lands in the block its
+face table names, the blocks' inside masks are exactly the inside rows, padding
+rows have no neighbours, the per-row projector entries are the exact transpose of the
 per-atom supports, each block's atom list holds exactly the atoms with an entry
 in its rows, and every entry's slot names its own atom.  Any sanitizer report
 fails the test.
