@@ -81,6 +81,9 @@ def test_rayleigh_ritz(tiny):
     ritz, Xr = C.rayleigh_ritz(H.apply, Q)
     assert np.allclose(ritz, np.linalg.eigvalsh(Q.T @ Hd @ Q), atol=1e-12)
     assert np.allclose(Xr.T @ Xr, np.eye(7), atol=1e-12)
+    # Ritz condition: the rotated vectors diagonalise the projected operator,
+    # column j carrying the j-th (ascending) Ritz value
+    assert np.allclose(Xr.T @ Hd @ Xr, np.diag(ritz), atol=1e-10 * np.abs(ritz).max())
     U, _ = np.linalg.qr(np.random.default_rng(6).standard_normal((7, 7)))
     ritz2, _ = C.rayleigh_ritz(H.apply, Q @ U)
     assert np.allclose(ritz, ritz2, atol=1e-12)

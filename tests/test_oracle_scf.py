@@ -150,6 +150,25 @@ def test_sad_density_normalised():
     assert abs(g.h ** 3 * rho.sum() - 5) < 1e-12 and (rho > 0).all()
 
 
+def test_density_counts_two_electrons_per_occupied_state():
+    # with orthonormal columns X the orbitals X_i / h^(3/2) are normalised in
+    # the grid quadrature, and each occupied state holds two electrons:
+    # h^3 sum rho = 2 n_occ.  The density is the diagonal of the projector on
+    # the occupied span, so a rotation inside the occupied columns and any
+    # change of the other columns leave it unchanged.
+    h = 0.7
+    X, _ = np.linalg.qr(np.random.default_rng(8).standard_normal((500, 12)))
+    for n_occ in (1, 5, 12):
+        rho = S.density(X, n_occ, h)
+        assert abs(h ** 3 * rho.sum() - 2 * n_occ) < 1e-12 and (rho >= 0).all()
+    U, _ = np.linalg.qr(np.random.default_rng(9).standard_normal((5, 5)))
+    Y = X.copy()
+    Y[:, :5] = X[:, :5] @ U
+    Y[:, 5:] = np.random.default_rng(10).standard_normal((500, 7))
+    ref = S.density(X, 5, h)
+    assert np.allclose(S.density(Y, 5, h), ref, rtol=0, atol=1e-13 * ref.max())
+
+
 _D = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
 H_POS = [[0, 0, 0], [_D, _D, _D], [_D, -_D, -_D], [-_D, _D, -_D], [-_D, -_D, _D]]
 
