@@ -8,19 +8,13 @@ import pytest
 from numpy.polynomial import chebyshev as npcheb
 
 from oracle import chfsi as C
-from oracle import grid as G
-from oracle import hamiltonian as OH
+
+import oracle_systems
 
 
 @pytest.fixture(scope="module")
 def tiny():
-    pos = np.array([[0.2, -0.3, 0.1], [2.4, 2.1, -2.2], [-1.6, 1.2, 1.4]])
-    species = np.array([0, 0, 1], np.int32)
-    g = G.build_grid(6.0, 0.8)
-    H = OH.build_hamiltonian(g, pos, species, OH.PseudoParams(h_s=2.0, h_p=0.5))
-    Hd = H.dense()
-    lam, V = np.linalg.eigh(Hd)
-    return H, Hd, lam, V
+    return oracle_systems.tiny()
 
 
 def test_filter_equals_polynomial_on_eigenpairs(tiny):

@@ -1,0 +1,419 @@
+"""Planted mistakes in the oracle, on the CPU.
+
+Each case patches one plausible slip into one oracle function (a dropped
+term or factor, a flipped sign, a wrong index or axis, a transposed
+operand) and runs the committed pins that cover that function; at least one
+of them must fail.  This shows that the pins constrain the oracle beyond
+restating its formulas.  The mistakes live only in this file, as wrong
+copies or wrappers of oracle functions; nothing here touches the HIP path.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.special import erf
+
+from oracle import chfsi as C
+from oracle import grid as G
+from oracle import hamiltonian as OH
+from oracle import scf as S
+from oracle import unet as U
+
+import oracle_systems
+import test_oracle_chfsi as TC
+import test_oracle_grid as TG
+import test_oracle_hamiltonian as TH
+import test_oracle_scf as TS
+import test_oracle_unet as TU
+
+# the oracle as written, for wrappers that plant a slip around it
+LANCZOS = C.lanczos_bound
+LAPLACIAN = OH.laplacian
+PROJECTORS = OH.projector_matrix
+HILBERT = G.hilbert_index3
+CONV3D = U.conv3d
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev filter, Lanczos bound, Cholesky-QR, Rayleigh-Ritz
+# ---------------------------------------------------------------------------
+def filter_scalars_beta_squared(m, a, b, a0):
+    e, c = (b - a) / 2.0, (b + a) / 2.0
+    s1 = e / (a0 - c)
+    out, s = [(s1 / e, c, 0.0)], s1
+    for _ in range(2, m + 1):
+        sn = 1.0 / (2.0 / s1 - s)
+        out.append((2.0 * sn / e, c, sn * sn))          # slip: sigma_{k+1}^2 for sigma_k sigma_{k+1}
+        s = sn
+    return out
+
+
+def filter_scalars_sigma1_sign(m, a, b, a0):
+    e, c = (b - a) / 2.0, (b + a) / 2.0
+    s1 = e / (c - a0)                                    # slip: sign of sigma_1
+    out, s = [(s1 / e, c, 0.0)], s1
+    for _ in range(2, m + 1):
+        sn = 1.0 / (2.0 / s1 - s)
+        out.append((2.0 * sn / e, c, s * sn))
+        s = sn
+    return out
+
+
+def filter_without_shift(apply_h, X, m, a, b, a0):
+    prev = cur = X
+    for k, (alpha, c, beta) in enumerate(C.filter_scalars(m, a, b, a0)):
+        nxt = alpha * apply_h(cur)                       # slip: (H - c) Y became H Y
+        if k > 0:
+            nxt = nxt - beta * prev
+        prev, cur = cur, nxt
+    return cur
+
+
+def filter_h_on_older_iterate(apply_h, X, m, a, b, a0):
+    prev = cur = X
+    for k, (alpha, c, beta) in enumerate(C.filter_scalars(m, a, b, a0)):
+        nxt = alpha * (apply_h(prev) - c * cur)          # slip: H applied to Y_{k-2}
+        if k > 0:
+            nxt = nxt - beta * prev
+        prev, cur = cur, nxt
+    return cur
+
+
+def lanczos_without_residual(apply_h, v0, k=10):
+    _, tmin, tmax = LANCZOS(apply_h, v0, k)
+    return tmax, tmin, tmax                              # slip: the bound misses ||f_k||
+
+
+def cholesky_qr_lower_factor(X):
+    R = np.linalg.cholesky(X.T @ X)                      # slip: the lower factor taken as R
+    return np.linalg.solve(R.T, X.T).T, R
+
+
+def rayleigh_ritz_rotation_transposed(apply_h, X):
+    Hs = X.T @ apply_h(X)
+    lam, Q = np.linalg.eigh(0.5 * (Hs + Hs.T))
+    return lam, X @ Q.T                                  # slip: rotated by Q^T
+
+
+def rayleigh_ritz_without_h(apply_h, X):
+    Hs = X.T @ X                                         # slip: the Gram matrix for X^T H X
+    lam, Q = np.linalg.eigh(0.5 * (Hs + Hs.T))
+    return lam, X @ Q
+
+
+# ---------------------------------------------------------------------------
+# Hamiltonian
+# ---------------------------------------------------------------------------
+def fd_weights_sign(p=6):
+    c = [Fraction(0)] * (p + 1)
+    for k in range(1, p + 1):
+        c[k] = Fraction(2 * (-1) ** k * math.factorial(p) ** 2,     # slip: (-1)^k for (-1)^(k+1)
+                        k * k * math.factorial(p - k) * math.factorial(p + k))
+    c[0] = -2 * sum(c[1:])
+    return c
+
+
+def laplacian_centre_once(g, nbr=None):
+    c0 = OH.fd_coefficients()[0] / g.h ** 2
+    return (LAPLACIAN(g, nbr) - (2.0 * c0) * sp.identity(g.n, format="csr")).tocsr()   # slip: c_0 once, not per axis
+
+
+def laplacian_signed_index(g, nbr=None):
+    if nbr is None:
+        nbr = G.neighbour_table(g)
+    c = OH.fd_coefficients() / (g.h * g.h)
+    rows, cols, vals = [np.arange(g.n)], [np.arange(g.n)], [np.full(g.n, 3.0 * c[0])]
+    for col, (_axis, k) in enumerate(G.offsets()):
+        ok = nbr[:, col] >= 0
+        rows.append(np.nonzero(ok)[0])
+        cols.append(nbr[ok, col].astype(np.int64))
+        vals.append(np.full(int(ok.sum()), c[k]))        # slip: c[k] for c[|k|] (negative k wraps)
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(g.n, g.n))
+
+
+def _vloc(g, pos, species, pp, limit_factor, arg):
+    z, w = pp.charges(species), pp.widths(species)
+    v = np.zeros(g.n)
+    for a in range(len(z)):
+        d = np.sqrt(((g.xyz - pos[a]) ** 2).sum(axis=1))
+        small = d < 1e-8
+        dd = np.where(small, 1.0, d)
+        v -= np.where(small, limit_factor * z[a] / (math.sqrt(math.pi) * w[a]), z[a] * erf(arg(dd, w[a])) / dd)
+    return v
+
+
+def vloc_limit_without_2(g, pos, species, pp):
+    return _vloc(g, pos, species, pp, 1.0, lambda d, w: d / w)      # slip: the r -> 0 limit loses its 2
+
+
+def vloc_erf_argument(g, pos, species, pp):
+    return _vloc(g, pos, species, pp, 2.0, lambda d, w: d * w)      # slip: erf(d r_loc) for erf(d / r_loc)
+
+
+def projectors_p_norm(g, pos, species, pp):
+    B, e = PROJECTORS(g, pos, species, pp)
+    # slip: N_p with r_c^3 in place of r_c^5 (the p columns come out r_c times too large)
+    scale = np.tile([1.0, pp.r_c, pp.r_c, pp.r_c], B.shape[1] // 4)
+    return (B @ sp.diags(scale)).tocsc(), e
+
+
+def _apply(self, X, kinetic, h3):
+    v = self.veff if X.ndim == 1 else self.veff[:, None]
+    Y = kinetic * (self.lap @ X) + v * X
+    if self.B.shape[1]:
+        e = self.kb_energy if X.ndim == 1 else self.kb_energy[:, None]
+        Y = Y + self.B @ (e * (h3(self) * (self.B.T @ X)))
+    return Y
+
+
+def apply_kb_without_h3(self, X):
+    return _apply(self, X, -0.5, lambda H: 1.0)                     # slip: quadrature weight h^3 dropped
+
+
+def apply_kinetic_sign(self, X):
+    return _apply(self, X, 0.5, lambda H: H.grid.h ** 3)            # slip: +1/2 L for -1/2 L
+
+
+# ---------------------------------------------------------------------------
+# grid, Hilbert order, neighbours
+# ---------------------------------------------------------------------------
+def hilbert_without_gray_decode(x, y, z, nbits):
+    X = [np.asarray(x, np.int64).copy(), np.asarray(y, np.int64).copy(), np.asarray(z, np.int64).copy()]
+    top = 1 << (nbits - 1)
+    q = top
+    while q > 1:
+        p = q - 1
+        for i in range(3):
+            hit = (X[i] & q) != 0
+            X[0] = np.where(hit, X[0] ^ p, X[0])
+            t = np.where(hit, 0, (X[0] ^ X[i]) & p)
+            X[0] = X[0] ^ t
+            X[i] = X[i] ^ t
+        q >>= 1
+    # slip: the Gray encoding across axes (X[1] ^= X[0], X[2] ^= X[1] and the
+    # correction word) is left out
+    idx = np.zeros_like(X[0])
+    for lvl in range(nbits - 1, -1, -1):
+        for i in range(3):
+            idx = (idx << 1) | ((X[i] >> lvl) & 1)
+    return idx
+
+
+def hilbert_z_first(x, y, z, nbits):
+    return HILBERT(z, y, x, nbits)                       # slip: bits interleaved z first
+
+
+def sphere_points_strict(radius, h):
+    n_r = int(math.floor(radius / h))
+    thr = math.floor((radius / h) ** 2 + 1e-9)
+    g = np.arange(-n_r, n_r + 1, dtype=np.int64)
+    i, j, k = np.meshgrid(g, g, g, indexing="ij")
+    inside = (i * i + j * j + k * k) < thr               # slip: points on the sphere dropped
+    return n_r, np.stack([i[inside], j[inside], k[inside]], axis=1)
+
+
+def neighbour_table_sign(g):
+    n = 2 * g.n_r + 1
+    cube = -np.ones((n, n, n), dtype=np.int64)
+    I = g.ijk + g.n_r
+    cube[I[:, 0], I[:, 1], I[:, 2]] = np.arange(g.n)
+    out = -np.ones((g.n, 36), dtype=np.int64)
+    for c, (axis, k) in enumerate(G.offsets()):
+        J = I.copy()
+        J[:, axis] -= k                                  # slip: offset applied with the wrong sign
+        ok = (J[:, axis] >= 0) & (J[:, axis] < n)
+        out[ok, c] = cube[J[ok, 0], J[ok, 1], J[ok, 2]]
+    return out.astype(np.int32)
+
+
+def offsets_positive_first():
+    return [(axis, k) for axis in range(3) for k in list(range(1, 7)) + list(range(-6, 0))]   # slip: +k before -k
+
+
+# ---------------------------------------------------------------------------
+# SCF pieces
+# ---------------------------------------------------------------------------
+def lda_potential_sign(rho):
+    ok = rho >= S.RHO_MIN
+    rs = (3.0 / (4.0 * math.pi * np.where(ok, rho, 1.0))) ** (1.0 / 3.0)
+    eps = S.lda_eps(rs)
+    v = eps + rs / 3.0 * S.lda_deps_drs(rs)              # slip: + (r_s / 3) d eps / d r_s
+    return np.where(ok, eps, 0.0), np.where(ok, v, 0.0)
+
+
+def anderson_extrapolation_sign(self, x, f):
+    if self.xs:
+        dX = np.stack([x - xp for xp in self.xs], axis=1)
+        dF = np.stack([f - fp for fp in self.fs], axis=1)
+        gamma = np.linalg.solve(dF.T @ dF, dF.T @ f)
+        xb, fb = x + dX @ gamma, f - dF @ gamma          # slip: + dX gamma
+    else:
+        xb, fb = x, f
+    self.xs.append(x.copy())
+    self.fs.append(f.copy())
+    if len(self.xs) > self.history:
+        self.xs.pop(0)
+        self.fs.pop(0)
+    return xb + self.beta * fb
+
+
+def _harris_foulkes(occ, hartree, xc_dc):
+    def hf(h, eig, n_occ, rho, vh, eps_xc, vxc, e_ii):
+        h3 = h ** 3
+        return (occ * float(eig[:n_occ].sum()) - h3 * float(rho @ (vh + xc_dc * vxc))
+                + hartree * h3 * float(rho @ vh) + h3 * float(rho @ eps_xc) + e_ii)
+    return hf
+
+
+def density_single_occupation(X, n_occ, h):
+    return (X[:, :n_occ] ** 2).sum(axis=1) / h ** 3      # slip: one electron per state
+
+
+def density_without_h3(X, n_occ, h):
+    return 2.0 * (X[:, :n_occ] ** 2).sum(axis=1)         # slip: grid normalisation dropped
+
+
+def ion_energy_all_ordered_pairs(pos, z):
+    e = 0.0
+    for a in range(len(z)):
+        d = np.sqrt(((pos - pos[a]) ** 2).sum(axis=1))
+        d[a] = np.inf
+        e += float((z[a] * z / d).sum())                 # slip: every pair counted twice
+    return e
+
+
+# ---------------------------------------------------------------------------
+# density network
+# ---------------------------------------------------------------------------
+def conv_flipped_kernel(x, w, b, stride=1):
+    return CONV3D(x, np.ascontiguousarray(w[:, :, ::-1, ::-1, ::-1]), b, stride)   # slip: convolution for correlation
+
+
+def silu_grad_first_term_only(z):
+    return 1.0 / (1.0 + np.exp(-z))                      # slip: sigma(z) for sigma(z)(1 + z(1 - sigma(z)))
+
+
+def adam_without_bias_correction(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    for k in p:
+        m[k] = b1 * m[k] + (1 - b1) * g[k]
+        v[k] = b2 * v[k] + (1 - b2) * g[k] * g[k]
+        p[k] = p[k] - lr * m[k] / (np.sqrt(v[k]) + eps)  # slip: no 1 / (1 - b^t) corrections
+
+
+def upsample_backward_mean(dy):
+    C_, D, H, W = dy.shape
+    return dy.reshape(C_, D // 2, 2, H // 2, 2, W // 2, 2).mean(axis=(2, 4, 6))   # slip: mean for sum
+
+
+# ---------------------------------------------------------------------------
+# the pins each slip is run against
+# ---------------------------------------------------------------------------
+PINS = {
+    "filter = polynomial on eigenpairs": lambda f: TC.test_filter_equals_polynomial_on_eigenpairs(f["tiny"]),
+    "filter scalars = Chebyshev ratios": lambda f: TC.test_filter_scalars_are_chebyshev_ratios(12, 0.1, 40.0, -0.5),
+    "filter normalisation": lambda f: TC.test_filter_scalars_normalisation(),
+    "Lanczos upper bound": lambda f: TC.test_lanczos_upper_bound(f["tiny"]),
+    "Cholesky-QR = Householder": lambda f: TC.test_cholesky_qr_matches_householder(),
+    "Rayleigh-Ritz": lambda f: TC.test_rayleigh_ritz(f["tiny"]),
+    "FD rationals": lambda f: TH.test_fd_exact_rationals(),
+    "FD symbol order": lambda f: TH.test_fd_symbol_order(),
+    "Kronecker sum on a box": lambda f: TH.test_laplacian_is_kronecker_sum_on_box(),
+    "plane wave": lambda f: TH.test_laplacian_plane_wave_interior(),
+    "V_loc closed form": lambda f: TH.test_local_potential_closed_form(),
+    "projector normalisation": lambda f: TH.test_projectors_normalised_and_orthogonal(),
+    "apply = dense": lambda f: TH.test_apply_matches_dense(),
+    "Hilbert bijection, unit steps": lambda f: TG.test_hilbert_bijection_and_unit_steps(3),
+    "Hilbert order 1 = Gray walk": lambda f: TG.test_hilbert_order1_is_gray_walk(),
+    "sphere points brute force": lambda f: TG.test_sphere_points_brute_force(3.5, 0.7),
+    "sums of three squares": lambda f: TG.test_sphere_point_counts_are_sums_of_three_squares(),
+    "neighbours brute force": lambda f: TG.test_neighbour_table_brute_force(),
+    "offset order": lambda f: TG.test_offsets_order(),
+    "LDA potential = derivative": lambda f: TS.test_lda_potential_is_derivative(),
+    "Anderson on a linear fixed point": lambda f: TS.test_anderson_solves_linear_fixed_point(),
+    "Harris-Foulkes = Kohn-Sham": lambda f: TS.test_harris_foulkes_equals_kohn_sham_at_self_consistency(f["sih4"]),
+    "density charge and invariance": lambda f: TS.test_density_counts_two_electrons_per_occupied_state(),
+    "ion-ion pairs": lambda f: TS.test_ion_energy_pair(),
+    "conv brute force": lambda f: TU.test_conv_matches_brute_force(3, 1),
+    "SiLU gradient": lambda f: TU.test_silu_grad(),
+    "Adam first step": lambda f: TU.test_adam_first_step_is_signed_lr(),
+    "upsample adjoint": lambda f: TU.test_upsample_adjoint(),
+}
+
+# slip -> (object patched, attribute, wrong version, pins that cover it)
+CASES = {
+    "filter beta_k squared": (C, "filter_scalars", filter_scalars_beta_squared,
+                              ["filter = polynomial on eigenpairs", "filter scalars = Chebyshev ratios"]),
+    "filter sigma_1 sign": (C, "filter_scalars", filter_scalars_sigma1_sign,
+                            ["filter = polynomial on eigenpairs", "filter scalars = Chebyshev ratios"]),
+    "filter drops the shift c": (C, "chebyshev_filter", filter_without_shift,
+                                 ["filter = polynomial on eigenpairs", "filter normalisation"]),
+    "filter applies H to Y_{k-2}": (C, "chebyshev_filter", filter_h_on_older_iterate,
+                                    ["filter = polynomial on eigenpairs", "filter normalisation"]),
+    "Lanczos bound without residual": (C, "lanczos_bound", lanczos_without_residual, ["Lanczos upper bound"]),
+    "Cholesky lower factor as R": (C, "cholesky_qr", cholesky_qr_lower_factor, ["Cholesky-QR = Householder"]),
+    "Ritz rotation transposed": (C, "rayleigh_ritz", rayleigh_ritz_rotation_transposed, ["Rayleigh-Ritz"]),
+    "Rayleigh-Ritz without H": (C, "rayleigh_ritz", rayleigh_ritz_without_h, ["Rayleigh-Ritz"]),
+    "FD weight sign": (OH, "fd_coefficients_exact", fd_weights_sign, ["FD rationals", "FD symbol order"]),
+    "Laplacian centre weight once": (OH, "laplacian", laplacian_centre_once,
+                                     ["Kronecker sum on a box", "plane wave"]),
+    "Laplacian signed weight index": (OH, "laplacian", laplacian_signed_index,
+                                      ["Kronecker sum on a box", "plane wave"]),
+    "V_loc limit without 2": (OH, "local_potential", vloc_limit_without_2, ["V_loc closed form"]),
+    "V_loc erf argument": (OH, "local_potential", vloc_erf_argument, ["V_loc closed form"]),
+    "p projector normalisation": (OH, "projector_matrix", projectors_p_norm, ["projector normalisation"]),
+    "KB term without h^3": (OH.Hamiltonian, "apply", apply_kb_without_h3, ["apply = dense"]),
+    "kinetic sign": (OH.Hamiltonian, "apply", apply_kinetic_sign, ["apply = dense"]),
+    "Hilbert without Gray encoding": (G, "hilbert_index3", hilbert_without_gray_decode,
+                                      ["Hilbert bijection, unit steps", "Hilbert order 1 = Gray walk"]),
+    "Hilbert bits z first": (G, "hilbert_index3", hilbert_z_first,
+                             ["Hilbert bijection, unit steps", "Hilbert order 1 = Gray walk"]),
+    "sphere boundary dropped": (G, "sphere_points", sphere_points_strict,
+                                ["sphere points brute force", "sums of three squares"]),
+    "neighbour offset sign": (G, "neighbour_table", neighbour_table_sign, ["neighbours brute force"]),
+    "offsets +k before -k": (G, "offsets", offsets_positive_first, ["offset order"]),
+    "LDA potential sign": (S, "lda", lda_potential_sign, ["LDA potential = derivative"]),
+    "PZ81 B coefficient sign": (S, "PZ_B", 0.048, ["LDA potential = derivative"]),
+    "Anderson extrapolation sign": (S.Anderson, "mix", anderson_extrapolation_sign,
+                                    ["Anderson on a linear fixed point"]),
+    "Harris-Foulkes full Hartree": (S, "harris_foulkes", _harris_foulkes(2.0, 1.0, 1.0),
+                                    ["Harris-Foulkes = Kohn-Sham"]),
+    "Harris-Foulkes single occupation": (S, "harris_foulkes", _harris_foulkes(1.0, 0.5, 1.0),
+                                         ["Harris-Foulkes = Kohn-Sham"]),
+    "Harris-Foulkes without xc double counting": (S, "harris_foulkes", _harris_foulkes(2.0, 0.5, 0.0),
+                                                  ["Harris-Foulkes = Kohn-Sham"]),
+    "density single occupation": (S, "density", density_single_occupation, ["density charge and invariance"]),
+    "density without h^3": (S, "density", density_without_h3, ["density charge and invariance"]),
+    "ion-ion pairs twice": (S, "ion_energy", ion_energy_all_ordered_pairs, ["ion-ion pairs"]),
+    "conv kernel flipped": (U, "conv3d", conv_flipped_kernel, ["conv brute force"]),
+    "SiLU gradient first term": (U, "silu_grad", silu_grad_first_term_only, ["SiLU gradient"]),
+    "Adam without bias correction": (U, "adam_step", adam_without_bias_correction, ["Adam first step"]),
+    "upsample backward mean": (U, "upsample_backward", upsample_backward_mean, ["upsample adjoint"]),
+}
+
+
+@pytest.fixture(scope="module")
+def systems():
+    return {"tiny": oracle_systems.tiny(), "sih4": oracle_systems.sih4_scf()}
+
+
+def _fails(pin, systems) -> bool:
+    try:
+        pin(systems)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_every_pin_passes_on_the_oracle_as_written(systems):
+    failing = [name for name, pin in PINS.items() if _fails(pin, systems)]
+    assert not failing, failing
+
+
+@pytest.mark.parametrize("slip", sorted(CASES))
+def test_planted_slip_fails_a_pin(slip, systems, monkeypatch):
+    target, attr, wrong, pins = CASES[slip]
+    monkeypatch.setattr(target, attr, wrong)
+    caught = [p for p in pins if _fails(PINS[p], systems)]
+    assert caught, f"no pin catches the slip '{slip}'"

@@ -13,7 +13,10 @@ from scipy.special import erf, eval_legendre
 from oracle import grid as G
 from oracle import hamiltonian as OH
 from oracle import scf as S
-from synth.cluster import BOHR_ANGSTROM, random_block
+from synth.cluster import random_block
+
+import oracle_systems
+from oracle_systems import H_POS
 
 
 def test_solid_harmonics_addition_theorem():
@@ -169,22 +172,9 @@ def test_density_counts_two_electrons_per_occupied_state():
     assert np.allclose(S.density(Y, 5, h), ref, rtol=0, atol=1e-13 * ref.max())
 
 
-_D = 1.48 / BOHR_ANGSTROM / math.sqrt(3)
-H_POS = [[0, 0, 0], [_D, _D, _D], [_D, -_D, -_D], [-_D, _D, -_D], [-_D, -_D, _D]]
-
-
 @pytest.fixture(scope="module")
 def sih4_scf():
-    pos = np.array(H_POS)
-    species = np.array([0, 1, 1, 1, 1], np.int32)
-    g = G.build_grid(float(np.sqrt((pos ** 2).sum(1)).max()) + 5.0, 0.7)
-    nbr = G.neighbour_table(g)
-    pp = OH.PseudoParams()
-    H = OH.build_hamiltonian(g, pos, species, pp)
-    st = S.ScfState(S.sad_density(g, pos, species, 8), random_block(g.n, 10, 5), np.zeros(g.n))
-    eii = S.ion_energy(pos, pp.charges(species))
-    reps = [S.scf_step(H, nbr, st, 8, 12, random_block(g.n, 1, 6)[:, 0], eii) for _ in range(30)]
-    return H, nbr, st, reps
+    return oracle_systems.sih4_scf()
 
 
 def test_scf_converges_and_is_self_consistent(sih4_scf):
