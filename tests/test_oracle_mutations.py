@@ -7,6 +7,7 @@ of them must fail.  This shows that the pins constrain the oracle beyond
 restating its formulas.  The mistakes live only in this file, as wrong
 copies or wrappers of oracle functions; nothing here touches the HIP path.
 """
+import dataclasses
 import math
 from fractions import Fraction
 
@@ -34,6 +35,8 @@ LAPLACIAN = OH.laplacian
 PROJECTORS = OH.projector_matrix
 HILBERT = G.hilbert_index3
 CONV3D = U.conv3d
+POINTWISE = OH.apply_at_points
+SOLID = S.solid_harmonics
 
 
 # ---------------------------------------------------------------------------
@@ -176,6 +179,11 @@ def apply_kinetic_sign(self, X):
     return _apply(self, X, 0.5, lambda H: H.grid.h ** 3)            # slip: +1/2 L for -1/2 L
 
 
+def pointwise_without_kb(ijk, x_at, h, radius, pos, species, pp, veff=None):
+    no_kb = dataclasses.replace(pp, h_s=0.0, h_p=0.0)   # slip: KB term dropped
+    return POINTWISE(ijk, x_at, h, radius, pos, species, no_kb, veff)
+
+
 # ---------------------------------------------------------------------------
 # grid, Hilbert order, neighbours
 # ---------------------------------------------------------------------------
@@ -226,6 +234,25 @@ def neighbour_table_sign(g):
         ok = (J[:, axis] >= 0) & (J[:, axis] < n)
         out[ok, c] = cube[J[ok, 0], J[ok, 1], J[ok, 2]]
     return out.astype(np.int32)
+
+
+def build_grid_local_xy_swapped(radius, h, ordering=G.ORDER_HILBERT):
+    n_r, pts = G.sphere_points(radius, h)
+    if ordering == G.ORDER_LEX:
+        order = np.lexsort((pts[:, 0], pts[:, 1], pts[:, 2]))
+        ijk = pts[order]
+        return G.Grid(h, radius, n_r, ijk, np.arange(len(ijk), dtype=np.int64), len(ijk), ordering,
+                      np.zeros((0, 3), np.int64))
+    I = pts + n_r
+    B = I // G.BLOCK
+    nb = (2 * n_r) // G.BLOCK + 1
+    key = G.hilbert_index3(B[:, 0], B[:, 1], B[:, 2], G.hilbert_bits(nb))
+    ukey, first = np.unique(key, return_index=True)
+    slot = np.searchsorted(ukey, key)
+    local = (I[:, 1] % G.BLOCK) + G.BLOCK * (I[:, 0] % G.BLOCK) + G.BLOCK ** 2 * (I[:, 2] % G.BLOCK)   # slip: y fastest
+    row = slot * G.BLOCK ** 3 + local
+    order = np.argsort(row, kind="stable")
+    return G.Grid(h, radius, n_r, pts[order], row[order], len(ukey) * G.BLOCK ** 3, ordering, B[first])
 
 
 def offsets_positive_first():
@@ -284,6 +311,87 @@ def ion_energy_all_ordered_pairs(pos, z):
     return e
 
 
+def lda_derivative_branch(rs):
+    sq, lnr = np.sqrt(rs), np.log(rs)
+    den = 1.0 + S.PZ_BETA1 * sq + S.PZ_BETA2 * rs
+    dec = np.where(rs >= 1.0, -S.PZ_GAMMA * (0.5 * S.PZ_BETA1 / sq + S.PZ_BETA2) / den ** 2,
+                   S.PZ_A / rs + S.PZ_C * lnr + S.PZ_D)   # slip: d(C r ln r)/dr taken as C ln r
+    return S.EX_CONST / rs ** 2 + dec
+
+
+def sad_density_unnormalised(g, pos, species, n_electrons, alpha_si=0.074, alpha_h=0.21):
+    rho = np.zeros(g.n)
+    for a in range(len(species)):
+        al = alpha_si if species[a] == 0 else alpha_h
+        z = 4.0 if species[a] == 0 else 1.0
+        rho += z * (al / math.pi) ** 1.5 * np.exp(-al * ((g.xyz - pos[a]) ** 2).sum(axis=1))
+    return rho * (n_electrons / rho.sum())                # slip: h^3 left out of the normalisation
+
+
+def solid_harmonics_unscaled_l2(x, y, z):
+    R = SOLID(x, y, z).copy()
+    R[4] *= 2.0                                          # slip: (3 z^2 - r^2) without its 1/2
+    return R
+
+
+def multipole_moments_without_h3(g, rho):
+    r = g.xyz
+    return S.solid_harmonics(r[:, 0], r[:, 1], r[:, 2]) @ rho   # slip: quadrature weight dropped
+
+
+def multipole_potential_exponent(q, pts):
+    R = S.solid_harmonics(pts[:, 0], pts[:, 1], pts[:, 2])
+    rr = np.sqrt((pts ** 2).sum(axis=1))
+    return ((q[:, None] * R) / rr[None, :] ** (2 * S.SH_L[:, None])).sum(axis=0)   # slip: r^(2l) for r^(2l+1)
+
+
+def ghost_points_signed_k(g, nbr):
+    owners, ks, pts = [], [], []
+    for col, (axis, k) in enumerate(G.offsets()):
+        out = np.nonzero(nbr[:, col] < 0)[0]
+        p = g.ijk[out].copy()
+        p[:, axis] += k
+        owners.append(out)
+        ks.append(np.full(len(out), k))                  # slip: signed k as the weight index
+        pts.append(p)
+    return np.concatenate(owners), np.concatenate(ks), np.concatenate(pts).astype(np.float64) * g.h
+
+
+def cg_beta_inverted(apply_a, b, x0, rtol=1e-12, max_iter=5000):
+    x = x0.copy()
+    r = b - apply_a(x)
+    p = r.copy()
+    rr = float(r @ r)
+    bn = float(np.linalg.norm(b))
+    it = 0
+    while math.sqrt(rr) > rtol * bn and it < max_iter:
+        ap = apply_a(p)
+        alpha = rr / float(p @ ap)
+        x += alpha * p
+        r -= alpha * ap
+        rr_new = float(r @ r)
+        p = r + (rr / rr_new) * p                        # slip: beta = |r_k|^2 / |r_k+1|^2
+        rr = rr_new
+        it += 1
+    return x, it
+
+
+def hartree_source_without_4pi(g, lap, nbr, rho, v0=None, rtol=1e-12):
+    owner, k, pts = S.ghost_points(g, nbr)
+    vb = S.multipole_potential(S.multipole_moments(g, rho), pts)
+    c = OH.fd_coefficients() / (g.h * g.h)
+    b = rho + np.bincount(owner, weights=c[k] * vb, minlength=g.n)   # slip: 4 pi rho written as rho
+    return S.conjugate_gradient(lambda v: -(lap @ v), b, np.zeros(g.n) if v0 is None else v0, rtol)
+
+
+def hartree_boundary_sign(g, lap, nbr, rho, v0=None, rtol=1e-12):
+    owner, k, pts = S.ghost_points(g, nbr)
+    vb = S.multipole_potential(S.multipole_moments(g, rho), pts)
+    c = OH.fd_coefficients() / (g.h * g.h)
+    b = 4.0 * math.pi * rho - np.bincount(owner, weights=c[k] * vb, minlength=g.n)   # slip: boundary term subtracted
+    return S.conjugate_gradient(lambda v: -(lap @ v), b, np.zeros(g.n) if v0 is None else v0, rtol)
+
+
 # ---------------------------------------------------------------------------
 # density network
 # ---------------------------------------------------------------------------
@@ -305,6 +413,37 @@ def adam_without_bias_correction(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, ep
 def upsample_backward_mean(dy):
     C_, D, H, W = dy.shape
     return dy.reshape(C_, D // 2, 2, H // 2, 2, W // 2, 2).mean(axis=(2, 4, 6))   # slip: mean for sum
+
+
+def conv_backward_dw_shift(x, w, dy, stride=1):
+    k = w.shape[2]
+    pad = k // 2
+    D, H, W = x.shape[1:]
+    if stride == 2:
+        full = np.zeros((dy.shape[0], D, H, W))
+        full[:, ::2, ::2, ::2] = dy
+        dy = full
+    db = dy.sum(axis=(1, 2, 3))
+    xp = np.pad(x, ((0, 0), (pad, pad), (pad, pad), (pad, pad)))
+    dw = np.zeros_like(w)
+    dxp = np.zeros_like(xp)
+    for dz in range(k):
+        for dy_ in range(k):
+            for dx in range(k):
+                sl = xp[:, k - 1 - dz:k - 1 - dz + D, dy_:dy_ + H, dx:dx + W]   # slip: tap z mirrored in dW
+                dw[:, :, dz, dy_, dx] = np.einsum("odhw,idhw->oi", dy, sl)
+                dxp[:, dz:dz + D, dy_:dy_ + H, dx:dx + W] += np.einsum("oi,odhw->idhw", w[:, :, dz, dy_, dx], dy)
+    return dxp[:, pad:pad + D, pad:pad + H, pad:pad + W], dw, db
+
+
+def highpass_unnormalised(box, sigma):
+    r = int(math.ceil(3.0 * sigma))
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-k * k / (2.0 * sigma * sigma))           # slip: weights not normalised to unit sum
+    out = np.asarray(box, dtype=np.float64)
+    for axis in range(3):
+        out = np.apply_along_axis(lambda v: np.convolve(v, g, mode="same"), axis, out)
+    return np.asarray(box, dtype=np.float64) - out
 
 
 # ---------------------------------------------------------------------------
@@ -339,6 +478,17 @@ PINS = {
     "SiLU gradient": lambda f: TU.test_silu_grad(),
     "Adam first step": lambda f: TU.test_adam_first_step_is_signed_lr(),
     "upsample adjoint": lambda f: TU.test_upsample_adjoint(),
+    "point-wise H X = grid operator": lambda f: TH.test_pointwise_apply_matches_grid_operator(),
+    "Hilbert block layout": lambda f: TG.test_ordering_layout(G.ORDER_HILBERT),
+    "LDA derivative, both branches": lambda f: TS.test_lda_energy_derivative_on_both_branches(),
+    "SAD normalisation": lambda f: TS.test_sad_density_normalised(),
+    "addition theorem": lambda f: TS.test_solid_harmonics_addition_theorem(),
+    "multipole exterior": lambda f: TS.test_multipole_potential_exterior(),
+    "ghost points brute force": lambda f: TS.test_ghost_points_brute_force(),
+    "CG = dense solve": lambda f: TS.test_conjugate_gradient_matches_dense_solve(),
+    "Poisson: Gaussian charge": lambda f: TS.test_poisson_gaussian_charge((0.9, -0.6, 0.5)),
+    "conv backward finite differences": lambda f: TU.test_conv_backward_finite_differences(1),
+    "high-pass closed forms": lambda f: TU.test_gaussian_highpass_closed_forms(),
 }
 
 # slip -> (object patched, attribute, wrong version, pins that cover it)
@@ -390,6 +540,22 @@ CASES = {
     "SiLU gradient first term": (U, "silu_grad", silu_grad_first_term_only, ["SiLU gradient"]),
     "Adam without bias correction": (U, "adam_step", adam_without_bias_correction, ["Adam first step"]),
     "upsample backward mean": (U, "upsample_backward", upsample_backward_mean, ["upsample adjoint"]),
+    "point-wise H X drops the KB term": (OH, "apply_at_points", pointwise_without_kb,
+                                         ["point-wise H X = grid operator"]),
+    "block-local index y fastest": (G, "build_grid", build_grid_local_xy_swapped, ["Hilbert block layout"]),
+    "LDA derivative branch": (S, "lda_deps_drs", lda_derivative_branch, ["LDA derivative, both branches"]),
+    "SAD normalisation without h^3": (S, "sad_density", sad_density_unnormalised, ["SAD normalisation"]),
+    "solid harmonic l=2 scale": (S, "solid_harmonics", solid_harmonics_unscaled_l2,
+                                 ["addition theorem", "multipole exterior"]),
+    "multipole moments without h^3": (S, "multipole_moments", multipole_moments_without_h3,
+                                      ["multipole exterior"]),
+    "multipole exponent": (S, "multipole_potential", multipole_potential_exponent, ["multipole exterior"]),
+    "ghost points signed weight index": (S, "ghost_points", ghost_points_signed_k, ["ghost points brute force"]),
+    "CG beta inverted": (S, "conjugate_gradient", cg_beta_inverted, ["CG = dense solve"]),
+    "Poisson source without 4 pi": (S, "hartree", hartree_source_without_4pi, ["Poisson: Gaussian charge"]),
+    "Poisson boundary sign": (S, "hartree", hartree_boundary_sign, ["Poisson: Gaussian charge"]),
+    "conv dW tap mirrored": (U, "conv3d_backward", conv_backward_dw_shift, ["conv backward finite differences"]),
+    "high-pass weights unnormalised": (U, "gaussian_highpass", highpass_unnormalised, ["high-pass closed forms"]),
 }
 
 
