@@ -162,6 +162,11 @@ def test_density_net_shapes_accepted(fake_net, fake):
     B.box_to_rows(H, f32(D ** 3), D, 3, 30.0, None, vec())
     B.box_to_rows(H, f32(D ** 3), D, 3, 30.0, vec(), vec())
     assert calls[:4] == ["dnet_set_params", "dnet_forward", "dnet_mse", "dnet_backward"]
+    # inference and training pass flat boxes and patches; every cube edge up to 256 is recovered
+    # from the value count
+    for edge in range(1, 257):
+        net.forward(f32(edge ** 3), f32(edge ** 3))
+        assert net._n_out == edge ** 3
 
 
 @pytest.mark.parametrize("case", ["params short", "x not a cube", "y short", "dy short", "t short", "crop box short",
