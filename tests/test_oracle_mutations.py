@@ -302,6 +302,13 @@ def density_without_h3(X, n_occ, h):
     return 2.0 * (X[:, :n_occ] ** 2).sum(axis=1)         # slip: grid normalisation dropped
 
 
+def sre_in_hartree(h, rho_out, dv, n_electrons):
+    return math.sqrt(h ** 3 * float((rho_out * dv * dv).sum()) / n_electrons)   # slip: Hartree, not Rydberg
+
+
+def sre_without_root(h, rho_out, dv, n_electrons):
+    return 2.0 * h ** 3 * float((rho_out * dv * dv).sum()) / n_electrons       # slip: mean square, no root
+
 def ion_energy_all_ordered_pairs(pos, z):
     e = 0.0
     for a in range(len(z)):
@@ -474,6 +481,7 @@ PINS = {
     "Harris-Foulkes = Kohn-Sham": lambda f: TS.test_harris_foulkes_equals_kohn_sham_at_self_consistency(f["sih4"]),
     "density charge and invariance": lambda f: TS.test_density_counts_two_electrons_per_occupied_state(),
     "ion-ion pairs": lambda f: TS.test_ion_energy_pair(),
+    "SRE closed forms": lambda f: TS.test_sre_is_density_weighted_rms_of_the_potential_change_in_rydberg(),
     "conv brute force": lambda f: TU.test_conv_matches_brute_force(3, 1),
     "SiLU gradient": lambda f: TU.test_silu_grad(),
     "Adam first step": lambda f: TU.test_adam_first_step_is_signed_lr(),
@@ -536,6 +544,8 @@ CASES = {
     "density single occupation": (S, "density", density_single_occupation, ["density charge and invariance"]),
     "density without h^3": (S, "density", density_without_h3, ["density charge and invariance"]),
     "ion-ion pairs twice": (S, "ion_energy", ion_energy_all_ordered_pairs, ["ion-ion pairs"]),
+    "SRE in Hartree": (S, "sre_ry", sre_in_hartree, ["SRE closed forms"]),
+    "SRE without the root": (S, "sre_ry", sre_without_root, ["SRE closed forms"]),
     "conv kernel flipped": (U, "conv3d", conv_flipped_kernel, ["conv brute force"]),
     "SiLU gradient first term": (U, "silu_grad", silu_grad_first_term_only, ["SiLU gradient"]),
     "Adam without bias correction": (U, "adam_step", adam_without_bias_correction, ["Adam first step"]),

@@ -172,6 +172,21 @@ def test_density_counts_two_electrons_per_occupied_state():
     assert np.allclose(S.density(Y, 5, h), ref, rtol=0, atol=1e-13 * ref.max())
 
 
+def test_sre_is_density_weighted_rms_of_the_potential_change_in_rydberg():
+    # SRE = sqrt(int rho dV^2 / N_e) in Hartree, reported in Rydberg (1 Ha = 2 Ry)
+    g = G.build_grid(6.0, 0.7)
+    rho = S.sad_density(g, np.zeros((1, 3)), np.array([0], np.int32), 4)     # 4 electrons
+    # a uniform change of delta Ha everywhere: SRE = |delta| Ha = 2 |delta| Ry
+    assert abs(S.sre_ry(g.h, rho, np.full(g.n, 3e-3), 4) - 6e-3) < 1e-15
+    assert S.sre_ry(g.h, rho, np.zeros(g.n), 4) == 0.0
+    # a fraction f of the charge sees d1, the rest d2: the root of the weighted mean square
+    inner = (g.xyz ** 2).sum(1) < 9.0
+    f = g.h ** 3 * rho[inner].sum() / 4
+    assert 0.1 < f < 0.9
+    dv = np.where(inner, 0.01, -0.002)
+    assert abs(S.sre_ry(g.h, rho, dv, 4) - 2 * math.sqrt(f * 0.01 ** 2 + (1 - f) * 0.002 ** 2)) < 1e-15
+
+
 @pytest.fixture(scope="module")
 def sih4_scf():
     return oracle_systems.sih4_scf()
