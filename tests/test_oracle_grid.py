@@ -111,6 +111,13 @@ def test_hilbert_aligned_runs_fill_cubes(nbits):
             assert (c.min(0) % (1 << k) == 0).all()
 
 
+def test_hilbert_bits_is_the_smallest_cube_holding_the_blocks():
+    # 2^bits cells per edge hold n blocks per edge, and bits - 1 would not (at least one bit)
+    for n in range(1, 300):
+        b = G.hilbert_bits(n)
+        assert 2 ** b >= n and (b == 1 or 2 ** (b - 1) < n), n
+
+
 def test_hilbert_order1_is_gray_walk():
     _, cells = _curve(1)
     gray = [i ^ (i >> 1) for i in range(8)]

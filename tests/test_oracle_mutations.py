@@ -213,6 +213,9 @@ def hilbert_z_first(x, y, z, nbits):
     return HILBERT(z, y, x, nbits)                       # slip: bits interleaved z first
 
 
+def hilbert_bits_of_count(n_blocks_edge):
+    return max(1, int(n_blocks_edge).bit_length())    # slip: bits of n, not of n - 1
+
 def sphere_points_strict(radius, h):
     n_r = int(math.floor(radius / h))
     thr = math.floor((radius / h) ** 2 + 1e-9)
@@ -410,6 +413,10 @@ def silu_grad_first_term_only(z):
     return 1.0 / (1.0 + np.exp(-z))                      # slip: sigma(z) for sigma(z)(1 + z(1 - sigma(z)))
 
 
+def mse_sum(y, t):
+    diff = y - t
+    return float((diff * diff).sum()), 2.0 * diff     # slip: sum for mean (loss and gradient agree)
+
 def adam_without_bias_correction(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     for k in p:
         m[k] = b1 * m[k] + (1 - b1) * g[k]
@@ -472,6 +479,7 @@ PINS = {
     "apply = dense": lambda f: TH.test_apply_matches_dense(),
     "Hilbert bijection, unit steps": lambda f: TG.test_hilbert_bijection_and_unit_steps(3),
     "Hilbert order 1 = Gray walk": lambda f: TG.test_hilbert_order1_is_gray_walk(),
+    "Hilbert bits minimal": lambda f: TG.test_hilbert_bits_is_the_smallest_cube_holding_the_blocks(),
     "sphere points brute force": lambda f: TG.test_sphere_points_brute_force(3.5, 0.7),
     "sums of three squares": lambda f: TG.test_sphere_point_counts_are_sums_of_three_squares(),
     "neighbours brute force": lambda f: TG.test_neighbour_table_brute_force(),
@@ -485,6 +493,7 @@ PINS = {
     "conv brute force": lambda f: TU.test_conv_matches_brute_force(3, 1),
     "SiLU gradient": lambda f: TU.test_silu_grad(),
     "Adam first step": lambda f: TU.test_adam_first_step_is_signed_lr(),
+    "MSE closed forms": lambda f: TU.test_mse_is_the_mean_square_and_its_gradient(),
     "upsample adjoint": lambda f: TU.test_upsample_adjoint(),
     "point-wise H X = grid operator": lambda f: TH.test_pointwise_apply_matches_grid_operator(),
     "Hilbert block layout": lambda f: TG.test_ordering_layout(G.ORDER_HILBERT),
@@ -527,6 +536,7 @@ CASES = {
                                       ["Hilbert bijection, unit steps", "Hilbert order 1 = Gray walk"]),
     "Hilbert bits z first": (G, "hilbert_index3", hilbert_z_first,
                              ["Hilbert bijection, unit steps", "Hilbert order 1 = Gray walk"]),
+    "Hilbert bits of n": (G, "hilbert_bits", hilbert_bits_of_count, ["Hilbert bits minimal"]),
     "sphere boundary dropped": (G, "sphere_points", sphere_points_strict,
                                 ["sphere points brute force", "sums of three squares"]),
     "neighbour offset sign": (G, "neighbour_table", neighbour_table_sign, ["neighbours brute force"]),
@@ -548,6 +558,7 @@ CASES = {
     "SRE without the root": (S, "sre_ry", sre_without_root, ["SRE closed forms"]),
     "conv kernel flipped": (U, "conv3d", conv_flipped_kernel, ["conv brute force"]),
     "SiLU gradient first term": (U, "silu_grad", silu_grad_first_term_only, ["SiLU gradient"]),
+    "MSE summed": (U, "mse", mse_sum, ["MSE closed forms"]),
     "Adam without bias correction": (U, "adam_step", adam_without_bias_correction, ["Adam first step"]),
     "upsample backward mean": (U, "upsample_backward", upsample_backward_mean, ["upsample adjoint"]),
     "point-wise H X drops the KB term": (OH, "apply_at_points", pointwise_without_kb,

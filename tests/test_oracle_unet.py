@@ -96,6 +96,19 @@ def test_network_gradient_finite_differences():
             assert abs(num - g[name][idx]) < 1e-6 * max(1e-3, abs(num)), (name, num, g[name][idx])
 
 
+def test_mse_is_the_mean_square_and_its_gradient():
+    # a uniform offset c: loss c^2 and gradient 2c/n everywhere; one element off by d: d^2 / n
+    t = np.random.default_rng(2).standard_normal((1, 4, 4, 4))
+    n = t.size
+    loss, dy = U.mse(t + 0.3, t)
+    assert abs(loss - 0.09) < 1e-15 and np.allclose(dy, 0.6 / n, rtol=1e-14)
+    y = t.copy()
+    y[0, 1, 2, 3] += 0.5
+    loss, dy = U.mse(y, t)
+    assert abs(loss - 0.25 / n) < 1e-15
+    assert abs(dy[0, 1, 2, 3] - 1.0 / n) < 1e-15 and np.count_nonzero(dy) == 1
+
+
 def test_adam_first_step_is_signed_lr():
     p = {"a": np.array([1.0, -2.0, 3.0])}
     g = {"a": np.array([0.5, -4.0, 1e-3])}
