@@ -50,6 +50,13 @@ def parse():
     return ap.parse_args()
 
 
+def alg_bytes_per_launch(n_points: int, nvec: int, elem_bytes: int, degree: int) -> float:
+    """Algorithmic HBM bytes of one H X + recurrence launch, averaged over a
+    degree-m filter pass: every launch reads Y_k and writes Y_{k+1}, and all
+    but the first also read Y_{k-1}, so a pass moves N nvec b (2 + 3 (m - 1))."""
+    return n_points * nvec * elem_bytes * (2 + 3 * (degree - 1)) / degree
+
+
 def kernel_source_hash() -> str:
     """SHA-256 of the H X kernel source (the counters in profiles/ name it)."""
     import hashlib
@@ -218,13 +225,10 @@ def main():
 
     n_pts = H.n_points
     value = n_pts * nvec / (ms / 1e3)
-    # algorithmic bytes of the H X + recurrence launches: every launch reads Y_k
-    # and writes Y_{k+1}; all but the first of each filter pass also read Y_{k-1}
     launches = tm["hx_launches"]
-    per_pass_bytes = n_pts * nvec * es * (2 + 3 * (wl.degree - 1))
-    alg_bytes_per_launch = per_pass_bytes / wl.degree
+    alg_bytes = alg_bytes_per_launch(n_pts, nvec, es, wl.degree)
     hx_avg_s = tm["hx_ms"] / 1e3 / max(1, launches)
-    achieved = alg_bytes_per_launch / hx_avg_s / 1e9
+    achieved = alg_bytes / hx_avg_s / 1e9
     kernel = ("hx_generic_kernel" if generic else "hx_tiled_kernel")
     # HBM traffic from the committed counter runs, only if they were taken on
     # the kernel source as it is now
@@ -253,7 +257,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "avg_launch_ms": hx_avg_s * 1e3,
-                     "alg_bytes_per_launch": alg_bytes_per_launch,
+                     "alg_bytes_per_launch": alg_bytes,
                      "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"]),
                      "kb_gather_launches": tm["gather_launches"]},
         "wall_s": wall,

@@ -43,3 +43,15 @@ def test_committed_traffic_record_is_consistent():
     assert rec["write_kib"] * 1024 == 53_417_472 * 256 * 4
     assert 1.9 < rec["fetch_scale"] < 2.1 and rec["write_scale"] == 1.0
     assert len(rec["source_sha256"]) == 64
+
+
+def test_algorithmic_bytes_per_launch():
+    """16 nm, 256 FP32 vectors, degree 16: 49,925,477 points x 256 x 4 B x (2 + 3 x 15) / 16
+    = 150,175,834,816 B per launch; a degree-1 pass only reads Y_0 and writes Y_1."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.alg_bytes_per_launch(49_925_477, 256, 4, 16) == 150_175_834_816
+    assert bench.alg_bytes_per_launch(1000, 8, 8, 1) == 1000 * 8 * 8 * 2
+    # FP64 doubles the bytes; a long pass tends to three block passes per launch
+    assert bench.alg_bytes_per_launch(10, 4, 8, 3) == 2 * bench.alg_bytes_per_launch(10, 4, 4, 3)
+    assert abs(bench.alg_bytes_per_launch(1, 1, 1, 10 ** 6) - 3) < 1e-5
