@@ -485,6 +485,7 @@ PINS = {
     "neighbours brute force": lambda f: TG.test_neighbour_table_brute_force(),
     "offset order": lambda f: TG.test_offsets_order(),
     "LDA potential = derivative": lambda f: TS.test_lda_potential_is_derivative(),
+    "PZ81 slope continuity": lambda f: TS.test_lda_correlation_slope_continuous_at_rs_1(),
     "Anderson on a linear fixed point": lambda f: TS.test_anderson_solves_linear_fixed_point(),
     "Harris-Foulkes = Kohn-Sham": lambda f: TS.test_harris_foulkes_equals_kohn_sham_at_self_consistency(f["sih4"]),
     "density charge and invariance": lambda f: TS.test_density_counts_two_electrons_per_occupied_state(),
@@ -543,6 +544,8 @@ CASES = {
     "offsets +k before -k": (G, "offsets", offsets_positive_first, ["offset order"]),
     "LDA potential sign": (S, "lda", lda_potential_sign, ["LDA potential = derivative"]),
     "PZ81 B coefficient sign": (S, "PZ_B", 0.048, ["LDA potential = derivative"]),
+    "PZ81 A coefficient mistyped": (S, "PZ_A", 0.0331, ["LDA potential = derivative", "PZ81 slope continuity"]),
+    "PZ81 C coefficient sign": (S, "PZ_C", -0.0020, ["LDA potential = derivative", "PZ81 slope continuity"]),
     "Anderson extrapolation sign": (S.Anderson, "mix", anderson_extrapolation_sign,
                                     ["Anderson on a linear fixed point"]),
     "Harris-Foulkes full Hartree": (S, "harris_foulkes", _harris_foulkes(2.0, 1.0, 1.0),

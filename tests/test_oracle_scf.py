@@ -93,6 +93,15 @@ def test_lda_energy_derivative_on_both_branches():
     assert np.allclose(S.lda_deps_drs(rs), num, rtol=1e-7)
 
 
+def test_lda_correlation_slope_continuous_at_rs_1():
+    # the PZ81 fit joins its two correlation forms at r_s = 1 with matching value and slope;
+    # the slope brings in the coefficients A and C, which vanish from the value there
+    d = 1e-9
+    lo, hi = S.lda_deps_drs(np.array([1.0 - d, 1.0 + d]))
+    assert abs(lo - hi) < 1e-4
+    assert abs(hi - S.lda_deps_drs(np.array([1.0 + 1e-3]))[0]) < 1e-3
+
+
 def test_conjugate_gradient_matches_dense_solve():
     rng = np.random.default_rng(4)
     n = 40
