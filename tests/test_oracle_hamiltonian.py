@@ -55,6 +55,33 @@ def test_laplacian_is_kronecker_sum_on_box():
     assert np.allclose(L, K, rtol=0, atol=1e-12)
 
 
+def test_dirichlet_box_spectrum():
+    """-1/2 L on an n^3 box with zero values outside: its spectrum is every sum of three
+    eigenvalues of the 1-D stencil matrix, all of them inside the symbol's range
+    [3 sigma(pi), 0] / h^2 (eigenvalues of a symmetric Toeplitz matrix lie in the range of
+    its symbol), and the lowest one tends to the continuum box's 3 pi^2 / (2 ((n + 1) h)^2).
+    With the wide stencil cut at the walls that limit is reached at first order: the
+    relative error halves when n doubles."""
+    from scipy.sparse.linalg import eigsh
+    c = OH.fd_coefficients()
+    sym_pi = c[0] + 2 * sum(c[k] * math.cos(k * math.pi) for k in range(1, 7))
+    n, h = 7, 0.6
+    lam = np.linalg.eigvalsh(OH.laplacian(_box_grid(n, h)).toarray())
+    col = np.zeros(n)
+    col[:7] = c
+    t = np.linalg.eigvalsh(sla.toeplitz(col)) / h ** 2
+    sums = np.sort((t[:, None, None] + t[None, :, None] + t[None, None, :]).ravel())
+    assert np.allclose(lam, sums, rtol=0, atol=1e-11 * np.abs(sums).max())
+    assert lam.max() < 0 and lam.min() > 3 * sym_pi / h ** 2
+    errs = []
+    for n in (9, 19, 39):
+        low = eigsh(-0.5 * OH.laplacian(_box_grid(n, h)), k=1, which="SA")[0][0]
+        exact = 3 * math.pi ** 2 / (2 * ((n + 1) * h) ** 2)
+        errs.append(abs(low - exact) / exact)
+    assert errs[2] < 0.012
+    assert 1.6 < errs[0] / errs[1] < 2.4 and 1.6 < errs[1] / errs[2] < 2.4
+
+
 def test_laplacian_plane_wave_interior():
     g = G.build_grid(8.0, 0.5)
     nbr = G.neighbour_table(g)

@@ -123,6 +123,9 @@ def laplacian_centre_once(g, nbr=None):
     return (LAPLACIAN(g, nbr) - (2.0 * c0) * sp.identity(g.n, format="csr")).tocsr()   # slip: c_0 once, not per axis
 
 
+def laplacian_over_h(g, nbr=None):
+    return (g.h * LAPLACIAN(g, nbr)).tocsr()             # slip: weights divided by h, not h^2
+
 def laplacian_signed_index(g, nbr=None):
     if nbr is None:
         nbr = G.neighbour_table(g)
@@ -474,6 +477,7 @@ PINS = {
     "FD symbol order": lambda f: TH.test_fd_symbol_order(),
     "Kronecker sum on a box": lambda f: TH.test_laplacian_is_kronecker_sum_on_box(),
     "plane wave": lambda f: TH.test_laplacian_plane_wave_interior(),
+    "Dirichlet box spectrum": lambda f: TH.test_dirichlet_box_spectrum(),
     "V_loc closed form": lambda f: TH.test_local_potential_closed_form(),
     "projector normalisation": lambda f: TH.test_projectors_normalised_and_orthogonal(),
     "apply = dense": lambda f: TH.test_apply_matches_dense(),
@@ -525,7 +529,9 @@ CASES = {
     "Rayleigh-Ritz without H": (C, "rayleigh_ritz", rayleigh_ritz_without_h, ["Rayleigh-Ritz"]),
     "FD weight sign": (OH, "fd_coefficients_exact", fd_weights_sign, ["FD rationals", "FD symbol order"]),
     "Laplacian centre weight once": (OH, "laplacian", laplacian_centre_once,
-                                     ["Kronecker sum on a box", "plane wave"]),
+                                     ["Kronecker sum on a box", "plane wave", "Dirichlet box spectrum"]),
+    "Laplacian over h, not h^2": (OH, "laplacian", laplacian_over_h,
+                                  ["Kronecker sum on a box", "plane wave", "Dirichlet box spectrum"]),
     "Laplacian signed weight index": (OH, "laplacian", laplacian_signed_index,
                                       ["Kronecker sum on a box", "plane wave"]),
     "V_loc limit without 2": (OH, "local_potential", vloc_limit_without_2, ["V_loc closed form"]),
