@@ -147,10 +147,6 @@ class Hamiltonian:
             Y = Y + self.B @ ((self.kb_energy if X.ndim == 1 else self.kb_energy[:, None]) * C)
         return Y
 
-    def kb_coefficients(self, X: np.ndarray) -> np.ndarray:
-        """C_alm,j = h^3 sum_q beta_alm(q) X(q, j), shape [4 N_Si, M]."""
-        return self.grid.h ** 3 * (self.B.T @ X)
-
     def dense(self) -> np.ndarray:
         """Dense H (tiny grids only)."""
         H = -0.5 * self.lap.toarray() + np.diag(self.veff)
