@@ -310,10 +310,18 @@ int chf_scf_create(chf_ham* ham, chf_ctx* ctx, const chf_scf_params* params, con
                    const double* v_lanczos_dev, chf_scf** out);
 int chf_scf_destroy(chf_scf* scf);
 
-/* One SCF step: V_eff from rho_in, Lanczos bound, ChFSI iterations on X
- * (filter, Cholesky-QR, Rayleigh-Ritz), rho_out, SRE, Harris-Foulkes energy,
- * Anderson mixing of rho_in.  eig_host (may be NULL) receives the nvec Ritz
- * values.  X: [n_rows][ldx] in filter_dtype; work: [n_rows][ldw], ldw >= nvec. */
+/* One SCF step (paper: the CheFSI paragraph, where the subspace is improved
+ * together with the potentials from one SCF iteration to the next, and the
+ * computational-details paragraph: LDA-PZ, four ChFSI iterations in the first
+ * step and one in each later step, SRE stopping criterion): V_eff from rho_in,
+ * Lanczos bound, ChFSI iterations on X (filter, Cholesky-QR, Rayleigh-Ritz),
+ * rho_out, SRE, Harris-Foulkes energy, Anderson mixing of rho_in.  eig_host
+ * (may be NULL) receives the nvec Ritz values.  X: [n_rows][ldx] in
+ * filter_dtype, caller-owned and updated in place; work: [n_rows][ldw],
+ * ldw >= nvec.  Errors: CHF_EINVAL (null argument, ld < nvec), CHF_ENONFINITE
+ * (NaN or Inf in V_eff, singular Anderson history), CHF_ENOTCONV (Poisson CG
+ * short of cg_rtol); errors of the filter, Cholesky-QR and Rayleigh-Ritz calls
+ * it makes pass through unchanged. */
 int scf_step(chf_scf* scf, void* X_dev, int64_t ldx, void* work_dev, int64_t ldw,
              chf_scf_report* report, double* eig_host);
 
