@@ -116,7 +116,12 @@ typedef struct {
 /* Builds the grid, the ordering, the neighbour and block tables, the
  * projector tables (host), uploads them, and computes V_loc on the device in
  * FP64; V_eff starts equal to V_loc.  The handle is bound to the device that
- * is current at the call. */
+ * is current at the call.  Errors: CHF_EINVAL (null argument, h or radius not
+ * positive and finite, radius <= h or radius / h >= 4000, bad ordering or
+ * dtypes mask, species other than 0 and 1, non-finite position, pseudopotential
+ * radii not positive, more than 2^31 rows or projector pairs), CHF_ENOMEM
+ * (host or device allocation), CHF_EHIP; on error *out is NULL (when out is
+ * not) and nothing stays allocated. */
 int ham_build(const chf_grid_desc* grid, const chf_atoms* atoms, const chf_pp* pp,
               void* stream, chf_ham** out);
 
