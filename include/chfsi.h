@@ -170,8 +170,13 @@ int ham_apply(chf_ham* ham, chf_dtype dtype, const void* X_dev, int64_t ldx, voi
 /* Degree-m scaled Chebyshev filter (paper: the CheFSI paragraph; the Zhou-Saad
  * form): X <- T_m((H - c) / e) X / T_m((a0 - c) / e), e = (b - a) / 2,
  * c = (b + a) / 2, evaluated by the three-term recurrence in place over X and
- * work (work: [n_rows][ldw], ldw >= nvec, same dtype; its contents on return
- * are unspecified).  Requires a < b and a0 < a; degree >= 1. */
+ * work (work: [n_rows][ldw], same dtype, disjoint from X, ldw >= 1; its
+ * contents on return are unspecified).  The vectors are independent, so a
+ * work block narrower than nvec is used column block by column block
+ * (min(nvec, ldw) vectors, rounded down to a multiple of 64 when ldw < nvec
+ * and ldw >= 64).  Requires a < b and a0 < a; 1 <= degree <= 1000.  Errors:
+ * CHF_EINVAL (null block, ld < nvec, bounds, X and work overlapping),
+ * CHF_EHIP. */
 int chebyshev_filter(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
                      double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
 
@@ -231,20 +236,40 @@ int chf_reserve(chf_ham* ham, chf_ctx* ctx, int op, chf_dtype dtype, int nvec, i
  * for checking that a sequence of calls allocates nothing). */
 int64_t chf_device_allocations(void);
 
-/* Cholesky-QR (paper: the subspace orthonormalisation of ChFSI):
- * S = X^T X (gram), S = R^T R in FP64, X <- X R^{-1} (the update in the block
- * precision).  Breakdown: the factorisation fails, or (FP64 blocks) a pivot
- * R_ii^2 falls below 1e-13 of column i's squared norm (the column is
- * numerically dependent on the ones before it).  On breakdown a shifted
- * Cholesky-QR (shift 1e-14 (FP64) / 1e-6 (FP32) of the mean diagonal) is
- * followed by a plain pass (counted in *fallbacks, may be NULL); CHF_ENOTPD
- * if that fails too. */
+/* Cholesky-QR (paper: the subspace orthonormalisation of ChFSI, CheFSI
+ * paragraph): S = X^T X (gram), S = R^T R in FP64, X <- X R^{-1} (the
+ * update in the block precision), in place on X [n_rows][ldx] (nvec columns,
+ * n_rows >= nvec).  gram_dtype: precision of the Gram products -- CHF_F64
+ * for an FP64 block; for an FP32 block CHF_F32 (FP32 MFMA products within
+ * row slices, the slices summed in FP64) or CHF_F64 (FP64 products of the
+ * widened block).  FP64 blocks take one pass; FP32 blocks take two (the
+ * second on the result of the first, CholQR2), which gives the same Q as one
+ * exact pass and removes the orthogonality loss of about kappa^2 u_32 that
+ * one FP32 pass leaves on an ill-conditioned (filtered) block.
+ * Breakdown of the first pass: the factorisation fails, or a pivot R_ii^2
+ * falls below a fraction of column i's squared norm (1e-13 with an FP64
+ * Gram, 1e-5 with an FP32 Gram): the column is numerically dependent on the
+ * ones before it.  Then an FP32 block with an FP32 Gram is redone with an
+ * FP64 Gram, and if that (or an FP64 block's pass) breaks down too, a
+ * shifted Cholesky-QR (shift 1e-14 (FP64) / 1e-6 (FP32) of the mean
+ * diagonal) is followed by a plain pass.  *fallbacks (may be NULL) receives
+ * the number of retries.  Errors: CHF_EINVAL (null block, nvec < 1, ldx <
+ * nvec, n_rows < nvec, n_rows or ldx >= 2^31, a gram_dtype other than
+ * CHF_F32 / CHF_F64, an FP64 block with an FP32 Gram), CHF_ENOTPD (the
+ * shifted pass breaks down too; X then holds the last successful pass),
+ * CHF_EHIP. */
 int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int64_t n_rows, int nvec,
-                   int* fallbacks, void* stream);
+                   chf_dtype gram_dtype, int* fallbacks, void* stream);
 
-/* Rayleigh-Ritz (paper: the CheFSI paragraph): W = H X blockwise into work
- * ([n_rows][ldw], ldw >= min(nvec, 256)), Hs = X^T W symmetrised (FP64),
- * Hs = Q diag(eig) Q^T (FP64), X <- X Q.  eig_host [nvec] ascending. */
+/* Rayleigh-Ritz (paper: the CheFSI paragraph): W = H X in column blocks of
+ * min(nvec, ldw) vectors through the work block ([n_rows][ldw], ldw >= 1,
+ * same dtype as X, disjoint from it), Hs = X^T W symmetrised (FP64),
+ * Hs = Q diag(eig) Q^T (FP64), X <- X Q in row panels of n_rows ldw / nvec
+ * rows, in place (the work block holds one panel at a time; Q rounded to
+ * FP32 for an FP32 block).  eig_host [nvec] ascending.  So the work block
+ * can be much narrower than X: at 7552 FP64 states a 256-wide work block is
+ * 1/30 of X.  Errors: CHF_EINVAL, CHF_ENOTCONV (eigensolver),
+ * CHF_ENONFINITE (a Ritz value is NaN or Inf; X is then unchanged). */
 int rayleigh_ritz(chf_ham* ham, chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec,
                   double* eig_host, void* work_dev, int64_t ldw, void* stream);
 
@@ -323,7 +348,10 @@ int chf_scf_destroy(chf_scf* scf);
  * rho_out, SRE, Harris-Foulkes energy, Anderson mixing of rho_in.  eig_host
  * (may be NULL) receives the nvec Ritz values.  X: [n_rows][ldx] in
  * filter_dtype, caller-owned and updated in place; work: [n_rows][ldw],
- * ldw >= nvec.  Errors: CHF_EINVAL (null argument, ld < nvec), CHF_ENONFINITE
+ * ldw >= 1 (the filter and Rayleigh-Ritz work in column blocks of
+ * min(nvec, ldw) vectors and Rayleigh-Ritz rotates X in row panels, so a
+ * narrow work block suffices), X and work disjoint.  Errors: CHF_EINVAL
+ * (null argument, ldx < nvec, ldw < 1, X and work overlapping), CHF_ENONFINITE
  * (NaN or Inf in V_eff, singular Anderson history), CHF_ENOTCONV (Poisson CG
  * short of cg_rtol); errors of the filter, Cholesky-QR and Rayleigh-Ritz calls
  * it makes pass through unchanged. */

@@ -82,7 +82,7 @@ _SIGS = {
     "chf_timer": [INT],
     "chf_timer_read": [P, P],
     "gram": [P, INT, P, I64, P, I64, I64, INT, INT, P, I64, P],
-    "orthonormalize": [P, INT, P, I64, I64, INT, P, P],
+    "orthonormalize": [P, INT, P, I64, I64, INT, INT, P, P],
     "rayleigh_ritz": [P, P, INT, P, I64, INT, P, P, I64, P],
     "chf_density": [P, INT, P, I64, INT, P, P],
     "chf_hartree": [P, P, P, P, D, INT, P, P],
@@ -340,8 +340,9 @@ class Hamiltonian:
              X.shape[1], _stream())
 
     def filter(self, X, work, degree: int, a: float, b: float, a0: float, generic: bool = False, nvec=None):
+        """X <- p_m(H) X in place; work may be narrower than X (column blocks)."""
         px, ldx = _block(X, self.n_rows, nvec=nvec or X.shape[1], what="X")
-        pw, ldw = _block(work, self.n_rows, like=X, nvec=nvec or X.shape[1], what="work")
+        pw, ldw = _block(work, self.n_rows, like=X, what="work")
         call("chf_filter_generic" if generic else "chebyshev_filter", self.handle, _dtype_code(X), px, ldx,
              nvec or X.shape[1], degree, a, b, a0, pw, ldw, _stream())
 
@@ -392,10 +393,14 @@ def gram(ctx: Context, A, B, S) -> None:
     call("gram", ctx.handle, _dtype_code(A), pa, lda, pb, ldb, A.shape[0], A.shape[1], B.shape[1], ps, lds, _stream())
 
 
-def orthonormalize(ctx: Context, X, nvec=None) -> int:
+def orthonormalize(ctx: Context, X, nvec=None, gram_dtype=None) -> int:
+    """Cholesky-QR of X in place; gram_dtype (CHF_F32 / CHF_F64) defaults to the
+    block's precision.  Returns the number of breakdown retries."""
     px, ldx = _block(X, nvec=nvec or X.shape[1], what="X")
     fb = C.c_int()
-    call("orthonormalize", ctx.handle, _dtype_code(X), px, ldx, X.shape[0], nvec or X.shape[1], C.byref(fb), _stream())
+    code = _dtype_code(X)
+    call("orthonormalize", ctx.handle, code, px, ldx, X.shape[0], nvec or X.shape[1],
+         code if gram_dtype is None else gram_dtype, C.byref(fb), _stream())
     return fb.value
 
 
@@ -442,7 +447,7 @@ class Scf:
         if (X.dtype == _torch_f64()) != self.filter_double:
             raise TypeError(f"X: dtype {X.dtype} is not the SCF's filter precision")
         px, ldx = _block(X, self.n_rows, nvec=self.nvec, what="X")
-        pw, ldw = _block(work, self.n_rows, like=X, nvec=self.nvec, what="work")
+        pw, ldw = _block(work, self.n_rows, like=X, what="work")
         rep = ScfReport()
         eig = np.zeros(self.nvec, np.float64)
         call("scf_step", self.handle, px, ldx, pw, ldw, C.byref(rep), P(eig.ctypes.data))

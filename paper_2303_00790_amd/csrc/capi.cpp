@@ -89,36 +89,20 @@ static void check_block(const chf_ham* H, int dtype, const void* p, int64_t ld, 
     (void)H;
 }
 
+// The two blocks of a call that reads one while it writes the other must not
+// share memory: [n_rows][ld] spans of each may not overlap.
+void check_disjoint(const chf_ham* H, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
+                    const char* what) {
+    const size_t es = dsize(dtype);
+    const char* a = static_cast<const char*>(A);
+    const char* b = static_cast<const char*>(B);
+    const size_t span_a = size_t(H->grid.n_rows) * size_t(lda) * es, span_b = size_t(H->grid.n_rows) * size_t(ldb) * es;
+    CHF_REQUIRE(a + span_a <= b || b + span_b <= a, "%s overlap", what);
+}
+
 }  // namespace chf
 
 namespace chf {
-// Degree-m scaled filter.  With e = (b - a) / 2, c = (b + a) / 2 and
-// sigma_k = T_{k-1}(t0) / T_k(t0), t0 = (a0 - c) / e, the normalised
-// iterates Y_k = T_k((H - c) / e) X / T_k(t0) obey
-//   Y_1 = (sigma_1 / e) (H - c) X,
-//   Y_k = (2 sigma_k / e) (H - c) Y_{k-1} - sigma_{k-1} sigma_k Y_{k-2},
-//   sigma_1 = e / (a0 - c), sigma_k = 1 / (2 / sigma_1 - sigma_{k-1}).
-// Y_k overwrites Y_{k-2} in place (X for even k, work for odd k).
-template <class T>
-static void run_filter(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b, double a0,
-                       hipStream_t s, int force_kernel) {
-    const double e = (b - a) / 2, c = (b + a) / 2;
-    const double sigma1 = e / (a0 - c);
-    double sigma = sigma1;
-    hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, nvec, sigma1 / e, c, 0.0, s, force_kernel);
-    for (int k = 2; k <= m; ++k) {
-        const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
-        const double alpha = 2.0 * sigma_next / e, beta = sigma * sigma_next;
-        if (k % 2 == 0)
-            hx_step<T>(H, W, ldw, X, ldx, X, ldx, nvec, alpha, c, beta, s, force_kernel);
-        else
-            hx_step<T>(H, X, ldx, W, ldw, W, ldw, nvec, alpha, c, beta, s, force_kernel);
-        sigma = sigma_next;
-    }
-    if (m % 2 == 1)
-        HIP_CHECK(hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), W, size_t(ldw) * sizeof(T), size_t(nvec) * sizeof(T),
-                                   size_t(H->grid.n_rows), hipMemcpyDeviceToDevice, s));
-}
 
 static int filter_impl(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
                        double a0, void* work, int64_t ldw, void* stream, int force_kernel) {
@@ -126,16 +110,17 @@ static int filter_impl(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nv
         CHF_REQUIRE(H, force_kernel ? "chf_filter_generic: null handle" : "chebyshev_filter: null handle");
         check_device(H);
         check_block(H, dtype, X, ldx, nvec, "chebyshev_filter X");
-        check_block(H, dtype, work, ldw, nvec, "chebyshev_filter work");
+        check_block(H, dtype, work, ldw, std::min<int64_t>(nvec, ldw), "chebyshev_filter work");
+        check_disjoint(H, dtype, X, ldx, work, ldw, "chebyshev_filter: X and work");
         CHF_REQUIRE(degree >= 1 && degree <= 1000, "chebyshev_filter: degree must be in [1, 1000]");
         CHF_REQUIRE(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0), "chebyshev_filter: non-finite bounds");
         CHF_REQUIRE(a < b && a0 < a, "chebyshev_filter: need a0 < a < b");
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (dtype == CHF_F64)
-            run_filter<double>(H, static_cast<double*>(X), ldx, static_cast<double*>(work), ldw, nvec, degree, a, b, a0, s,
-                               force_kernel);
+            filter_run<double>(H, static_cast<double*>(X), ldx, static_cast<double*>(work), ldw, nvec, degree, a, b, a0,
+                               s, force_kernel);
         else
-            run_filter<float>(H, static_cast<float*>(X), ldx, static_cast<float*>(work), ldw, nvec, degree, a, b, a0, s,
+            filter_run<float>(H, static_cast<float*>(X), ldx, static_cast<float*>(work), ldw, nvec, degree, a, b, a0, s,
                               force_kernel);
     });
 }
@@ -396,11 +381,7 @@ int ham_apply(chf_ham* H, chf_dtype dtype, const void* X, int64_t ldx, void* Y, 
         check_device(H);
         check_block(H, dtype, X, ldx, nvec, "ham_apply X");
         check_block(H, dtype, Y, ldy, nvec, "ham_apply Y");
-        const size_t es = dsize(dtype);
-        const char* xb = static_cast<const char*>(X);
-        const char* yb = static_cast<const char*>(Y);
-        const size_t span_x = size_t(H->grid.n_rows) * size_t(ldx) * es, span_y = size_t(H->grid.n_rows) * size_t(ldy) * es;
-        CHF_REQUIRE(xb + span_x <= yb || yb + span_y <= xb, "ham_apply: X and Y overlap");
+        check_disjoint(H, dtype, X, ldx, Y, ldy, "ham_apply: X and Y");
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (dtype == CHF_F64)
             hx_step<double>(H, static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, nullptr, 0, nvec, 1.0, 0.0,

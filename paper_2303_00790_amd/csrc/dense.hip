@@ -338,19 +338,71 @@ __global__ void __launch_bounds__(256) pivot_ratio_kernel(int m, const double* _
     }
 }
 
-// FP64 blocks: a Cholesky pivot below this fraction of its column's squared
-// norm marks the column as numerically dependent on the ones before it (the
-// factorisation "succeeds" on rounding noise); treated as a breakdown.
+// A Cholesky pivot R_ii^2 below this fraction of column i's squared norm
+// marks column i as numerically dependent on the ones before it (the
+// factorisation "succeeds" on rounding noise): treated as a breakdown.  The
+// fraction matches the precision of the Gram: an FP64 Gram resolves
+// R_ii^2 / S_ii down to ~1e-16, an FP32 Gram (FP32 products within row
+// slices) only to ~1e-6, and a first pass at that limit would leave the
+// factor too inaccurate for the second pass to repair.
 constexpr double kPivotRelF64 = 1e-13;
+constexpr double kPivotRelF32 = 1e-5;
 
-// Cholesky-QR on one block: S = X^T X, S = R^T R, X <- X R^{-1}.  Returns 0 or
-// the rocSOLVER info (> 0: leading minor not positive definite), or for FP64
-// blocks the 1-based index of a pivot below kPivotRelF64.
+__global__ void cast_panel_kernel(int64_t rows, int m, const float* __restrict__ X, int64_t ldx,
+                                  double* __restrict__ D) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= rows * m) return;
+    const int64_t r = idx / m;
+    const int c = int(idx - r * m);
+    D[idx] = double(X[r * ldx + c]);
+}
+
+// S[i][j] = S[j][i] for i > j (row-major): mirror the upper triangle
+__global__ void mirror_upper_kernel(int m, double* __restrict__ S) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(m) * m) return;
+    const int i = int(idx / m), j = int(idx % m);
+    if (i > j) S[idx] = S[int64_t(j) * m + i];
+}
+
+// S = X^T X of an FP32 block with FP64 products and sums: row panels of X are
+// widened to FP64 (at most kGramPartBytes of scratch) and accumulated into S
+// by FP64 GEMMs in panel order, then the upper triangle is mirrored.
+static void gram_f32_in_f64(chf_ctx* ctx, const float* X, int64_t ldx, int64_t n_rows, int m, double* S,
+                            hipStream_t s) {
+    const int64_t P = std::max<int64_t>(1, std::min<int64_t>(n_rows, int64_t(kGramPartBytes / (size_t(m) * 8))));
+    CHF_REQUIRE(P <= INT32_MAX, "gram: panel beyond 32-bit BLAS");
+    ctx->scratch2.ensure(size_t(P) * size_t(m) * 8);
+    double* D = ctx->scratch2.as<double>();
+    ROCBLAS_CHECK(rocblas_set_stream(ctx->blas, s));
+    const double one = 1.0, zero = 0.0;
+    for (int64_t r0 = 0; r0 < n_rows; r0 += P) {
+        const int64_t rows = std::min(P, n_rows - r0);
+        cast_panel_kernel<<<unsigned((rows * m + 255) / 256), 256, 0, s>>>(rows, m, X + r0 * ldx, ldx, D);
+        LAUNCH_CHECK();
+        // column-major D is m x rows (ld m); S (col-major = row-major) += D D^T
+        ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, m, m,
+                                    rocblas_int(rows), &one, D, m, D, m, r0 == 0 ? &zero : &one, S, m));
+    }
+    mirror_upper_kernel<<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(m, S);
+    LAUNCH_CHECK();
+}
+
+// One Cholesky-QR pass: S = X^T X (in the block precision, or in FP64 for an
+// FP32 block when gram64), S = R^T R in FP64, X <- X R^{-1} in the block
+// precision.  Returns 0, or the rocSOLVER info (> 0: leading minor not
+// positive definite), or the 1-based index of a pivot below the threshold of
+// the Gram's precision; X is unchanged unless 0 is returned.
 template <class T>
-static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, double shift_rel, hipStream_t s) {
+static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, double shift_rel, bool gram64,
+                       hipStream_t s) {
+    constexpr bool f64 = std::is_same<T, double>::value;
     double* S = mm_scratch(ctx, m, cholqr_extra(m));
     double* diag = reinterpret_cast<double*>(reinterpret_cast<char*>(S) + size_t(m) * m * (sizeof(double) + sizeof(float)) + 256);
-    gram_product<T>(ctx, X, ldx, X, ldx, n_rows, m, m, S, m, s);
+    if (!f64 && gram64)
+        gram_f32_in_f64(ctx, reinterpret_cast<const float*>(X), ldx, n_rows, m, S, s);
+    else
+        gram_product<T>(ctx, X, ldx, X, ldx, n_rows, m, m, S, m, s);
     if (shift_rel > 0) {
         double* tr = reinterpret_cast<double*>(ctx->info.p);
         trace_kernel<<<1, 256, 0, s>>>(m, S, tr);
@@ -365,29 +417,25 @@ static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, d
     // column-major U with S = U^T U, i.e. R = U.
     int* dinfo = reinterpret_cast<int*>(reinterpret_cast<char*>(S) + size_t(m) * m * sizeof(double) +
                                         size_t(m) * m * sizeof(float));
-    constexpr bool f64 = std::is_same<T, double>::value;
-    if (f64) {
-        diag_copy_kernel<<<(m + 255) / 256, 256, 0, s>>>(m, S, diag);
-        LAUNCH_CHECK();
-    }
+    diag_copy_kernel<<<(m + 255) / 256, 256, 0, s>>>(m, S, diag);
+    LAUNCH_CHECK();
     ROCBLAS_CHECK(rocsolver_dpotrf(ctx->blas, rocblas_fill_upper, m, S, m, dinfo));
     double piv[2] = {1.0, 0.0};
-    if (f64) {
-        double* pr = reinterpret_cast<double*>(ctx->info.p) + 2;
-        pivot_ratio_kernel<<<1, 256, 0, s>>>(m, S, diag, pr);
-        LAUNCH_CHECK();
-        HIP_CHECK(hipMemcpyAsync(piv, pr, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
+    double* pr = reinterpret_cast<double*>(ctx->info.p) + 2;
+    pivot_ratio_kernel<<<1, 256, 0, s>>>(m, S, diag, pr);
+    LAUNCH_CHECK();
+    HIP_CHECK(hipMemcpyAsync(piv, pr, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     int info = 0;
     HIP_CHECK(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     if (info != 0) return info;
-    if (f64 && !(piv[0] >= kPivotRelF64)) return int(piv[1]) + 1;
+    const double thr = (f64 || gram64) ? kPivotRelF64 : kPivotRelF32;
+    if (shift_rel == 0 && !(piv[0] >= thr)) return int(piv[1]) + 1;
     keep_upper_kernel<<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(m, S);
     LAUNCH_CHECK();
     // X is row-major [n_rows][ldx] = column-major Xc [m][n_rows] (ld ldx).
     // X R^{-1}  <=>  Xc <- R^{-T} Xc : left-side solve with U^T.
-    if (std::is_same<T, double>::value) {
+    if (f64) {
         const double one = 1.0;
         ROCBLAS_CHECK(rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
                                     rocblas_diagonal_non_unit, m, rocblas_int(n_rows), &one, S, m,
@@ -404,19 +452,38 @@ static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, d
     return 0;
 }
 
+// Cholesky-QR (CheFSI paragraph: orthonormalisation of the filtered block).
+// FP64 blocks: one pass.  FP32 blocks: two passes (CholQR2).  A filtered
+// block has a condition number of the order of |T_m(t0)|, so one pass with
+// FP32 arithmetic leaves an orthogonality error of about kappa^2 u_32; the
+// second pass on the nearly orthonormal result brings it down to the
+// rounding level.  The product of the two triangular factors is again upper
+// triangular with a positive diagonal, so the result is the same Q as that
+// of one exact pass.  Breakdown of the first pass: an FP32 block first
+// retries with an FP64 Gram (gram_dtype CHF_F64 starts there), then any
+// block takes a shifted pass; each retry is counted in *fallbacks.
 template <class T>
-void orthonormalize_t(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, int* fallbacks, hipStream_t s) {
+void orthonormalize_t(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, bool gram64, int* fallbacks,
+                      hipStream_t s) {
+    constexpr bool f64 = std::is_same<T, double>::value;
     int fb = 0;
-    int info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, s);
-    if (info != 0) {
-        // shifted Cholesky-QR followed by a plain pass (CholQR2 on the
-        // shifted factor): the shift makes the factorisation exist, the
-        // second pass restores orthonormality.
+    int info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, gram64, s);
+    if (info != 0 && !f64 && !gram64) {
         ++fb;
-        const double shift = std::is_same<T, double>::value ? 1e-14 : 1e-6;
-        info = cholqr_once<T>(ctx, X, ldx, n_rows, m, shift, s);
-        if (info == 0) info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, s);
+        gram64 = true;
+        info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, true, s);
     }
+    bool shifted = false;
+    if (info != 0) {
+        // shifted Cholesky-QR: the shift makes the factorisation exist; the
+        // plain pass after it restores orthonormality
+        ++fb;
+        shifted = true;
+        const double shift = f64 ? 1e-14 : 1e-6;
+        info = cholqr_once<T>(ctx, X, ldx, n_rows, m, shift, gram64, s);
+        if (info == 0) info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, gram64, s);
+    }
+    if (info == 0 && !f64 && !shifted) info = cholqr_once<T>(ctx, X, ldx, n_rows, m, 0.0, gram64, s);
     if (fallbacks) *fallbacks = fb;
     if (info != 0) fail(CHF_ENOTPD, "orthonormalize: Gram matrix not positive definite (minor %d)", info);
 }
@@ -447,26 +514,35 @@ void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double*
     if (info != 0) fail(CHF_ENOTCONV, "rayleigh_ritz: eigensolver did not converge (info %d)", info);
     for (int i = 0; i < m; ++i)
         if (!std::isfinite(eig_host[i])) fail(CHF_ENONFINITE, "rayleigh_ritz: non-finite Ritz value");
-    // Hs now holds Q column-major (column j = eigenvector j).  X Q (row-major)
-    // <=> Xc_new = Q^T Xc, computed into W in row panels of ldw / m ... W must
-    // hold all m columns: ldw >= m is required for the rotation.
-    if (ldw < m) fail(CHF_EINVAL, "rayleigh_ritz: work leading dimension must be >= nvec");
-    if (std::is_same<T, double>::value) {
-        const double one = 1.0, zero = 0.0;
-        ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, m,
-                                    rocblas_int(n_rows), m, &one, Hs, m, reinterpret_cast<const double*>(X),
-                                    rocblas_int(ldx), &zero, reinterpret_cast<double*>(W), rocblas_int(ldw)));
-    } else {
-        float* Q32 = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * sizeof(double));
+    // Hs now holds Q column-major (column j = eigenvector j).  X <- X Q in row
+    // panels, in place: a panel of P rows of X (row-major, = column-major
+    // Xc [m][P]) gives Qᵀ Xc, computed into the work block used as flat
+    // storage of P x m values (P = n_rows ldw / m), then copied back.
+    const int64_t P = std::max<int64_t>(1, std::min<int64_t>(n_rows, n_rows * ldw / m));
+    CHF_REQUIRE(P <= INT32_MAX, "rayleigh_ritz: panel beyond 32-bit BLAS");
+    float* Q32 = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * sizeof(double));
+    if (!std::is_same<T, double>::value) {
         cast_matrix_kernel<float><<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(int64_t(m) * m, Hs, Q32);
         LAUNCH_CHECK();
-        const float one = 1.0f, zero = 0.0f;
-        ROCBLAS_CHECK(rocblas_sgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, m,
-                                    rocblas_int(n_rows), m, &one, Q32, m, reinterpret_cast<const float*>(X),
-                                    rocblas_int(ldx), &zero, reinterpret_cast<float*>(W), rocblas_int(ldw)));
     }
-    HIP_CHECK(hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), W, size_t(ldw) * sizeof(T), size_t(m) * sizeof(T),
-                               size_t(n_rows), hipMemcpyDeviceToDevice, s));
+    for (int64_t r0 = 0; r0 < n_rows; r0 += P) {
+        const int64_t rows = std::min(P, n_rows - r0);
+        if (std::is_same<T, double>::value) {
+            const double one = 1.0, zero = 0.0;
+            ROCBLAS_CHECK(rocblas_dgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, m,
+                                        rocblas_int(rows), m, &one, Hs, m,
+                                        reinterpret_cast<const double*>(X + r0 * ldx), rocblas_int(ldx), &zero,
+                                        reinterpret_cast<double*>(W), m));
+        } else {
+            const float one = 1.0f, zero = 0.0f;
+            ROCBLAS_CHECK(rocblas_sgemm(ctx->blas, rocblas_operation_transpose, rocblas_operation_none, m,
+                                        rocblas_int(rows), m, &one, Q32, m,
+                                        reinterpret_cast<const float*>(X + r0 * ldx), rocblas_int(ldx), &zero,
+                                        reinterpret_cast<float*>(W), m));
+        }
+        HIP_CHECK(hipMemcpy2DAsync(X + r0 * ldx, size_t(ldx) * sizeof(T), W, size_t(m) * sizeof(T),
+                                   size_t(m) * sizeof(T), size_t(rows), hipMemcpyDeviceToDevice, s));
+    }
 }
 
 // three vectors of n_rows as 2-column blocks
@@ -573,17 +649,20 @@ int gram(chf_ctx* ctx, chf_dtype dtype, const void* A, int64_t lda, const void* 
     });
 }
 
-int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X, int64_t ldx, int64_t n_rows, int nvec, int* fallbacks,
-                   void* stream) {
+int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X, int64_t ldx, int64_t n_rows, int nvec, chf_dtype gram_dtype,
+                   int* fallbacks, void* stream) {
     return guard([&] {
         check_ctx_block(ctx, dtype, X, ldx, nvec, "orthonormalize");
+        if (gram_dtype != CHF_F32 && gram_dtype != CHF_F64) fail(CHF_EINVAL, "orthonormalize: bad Gram dtype");
+        if (dtype == CHF_F64 && gram_dtype != CHF_F64)
+            fail(CHF_EINVAL, "orthonormalize: an FP64 block needs an FP64 Gram");
         if (n_rows < nvec) fail(CHF_EINVAL, "orthonormalize: n_rows < nvec");
         if (n_rows >= (int64_t(1) << 31) || ldx >= (int64_t(1) << 31)) fail(CHF_EINVAL, "orthonormalize: block too large");
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (dtype == CHF_F64)
-            orthonormalize_t<double>(ctx, static_cast<double*>(X), ldx, n_rows, nvec, fallbacks, s);
+            orthonormalize_t<double>(ctx, static_cast<double*>(X), ldx, n_rows, nvec, true, fallbacks, s);
         else
-            orthonormalize_t<float>(ctx, static_cast<float*>(X), ldx, n_rows, nvec, fallbacks, s);
+            orthonormalize_t<float>(ctx, static_cast<float*>(X), ldx, n_rows, nvec, gram_dtype == CHF_F64, fallbacks, s);
     });
 }
 
@@ -683,8 +762,8 @@ namespace chf {
 template void dot_device<double>(chf_ctx*, int64_t, const double*, int64_t, const double*, int64_t, double*, hipStream_t);
 template void dot_device<float>(chf_ctx*, int64_t, const float*, int64_t, const float*, int64_t, double*, hipStream_t);
 template double dot_host<double>(chf_ctx*, int64_t, const double*, int64_t, const double*, int64_t, hipStream_t);
-template void orthonormalize_t<float>(chf_ctx*, float*, int64_t, int64_t, int, int*, hipStream_t);
-template void orthonormalize_t<double>(chf_ctx*, double*, int64_t, int64_t, int, int*, hipStream_t);
+template void orthonormalize_t<float>(chf_ctx*, float*, int64_t, int64_t, int, bool, int*, hipStream_t);
+template void orthonormalize_t<double>(chf_ctx*, double*, int64_t, int64_t, int, bool, int*, hipStream_t);
 template void rayleigh_ritz_t<float>(chf_ham*, chf_ctx*, float*, int64_t, int, double*, float*, int64_t, hipStream_t);
 template void rayleigh_ritz_t<double>(chf_ham*, chf_ctx*, double*, int64_t, int, double*, double*, int64_t, hipStream_t);
 }  // namespace chf

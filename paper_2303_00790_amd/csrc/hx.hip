@@ -914,6 +914,50 @@ void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z,
     }
 }
 
+// Degree-m scaled filter (CheFSI paragraph; the Zhou-Saad form).  With
+// e = (b - a) / 2, c = (b + a) / 2 and sigma_k = T_{k-1}(t0) / T_k(t0),
+// t0 = (a0 - c) / e, the normalised iterates Y_k = T_k((H - c) / e) X / T_k(t0)
+// obey
+//   Y_1 = (sigma_1 / e) (H - c) X,
+//   Y_k = (2 sigma_k / e) (H - c) Y_{k-1} - sigma_{k-1} sigma_k Y_{k-2},
+//   sigma_1 = e / (a0 - c), sigma_k = 1 / (2 / sigma_1 - sigma_{k-1}).
+// Y_k overwrites Y_{k-2} in place (X for even k, the work block for odd k).
+// The vectors are independent, so a work block narrower than the block is
+// used column block by column block: min(nvec, ldw) columns at a time (a
+// multiple of 64 when ldw allows, so that every block keeps the kernels'
+// vector-chunk alignment).
+template <class T>
+void filter_run(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b, double a0,
+                hipStream_t s, int force_kernel) {
+    const double e = (b - a) / 2, c = (b + a) / 2;
+    const double sigma1 = e / (a0 - c);
+    int64_t nb = std::min<int64_t>(nvec, ldw);
+    if (nb < nvec && nb >= 64) nb -= nb % 64;
+    for (int c0 = 0; c0 < nvec; c0 += int(nb)) {
+        const int w = int(std::min<int64_t>(nb, nvec - c0));
+        T* Xc = X + c0;
+        double sigma = sigma1;
+        hx_step<T>(H, Xc, ldx, W, ldw, nullptr, 0, w, sigma1 / e, c, 0.0, s, force_kernel);
+        for (int k = 2; k <= m; ++k) {
+            const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
+            const double alpha = 2.0 * sigma_next / e, beta = sigma * sigma_next;
+            if (k % 2 == 0)
+                hx_step<T>(H, W, ldw, Xc, ldx, Xc, ldx, w, alpha, c, beta, s, force_kernel);
+            else
+                hx_step<T>(H, Xc, ldx, W, ldw, W, ldw, w, alpha, c, beta, s, force_kernel);
+            sigma = sigma_next;
+        }
+        if (m % 2 == 1)
+            HIP_CHECK(hipMemcpy2DAsync(Xc, size_t(ldx) * sizeof(T), W, size_t(ldw) * sizeof(T), size_t(w) * sizeof(T),
+                                       size_t(H->grid.n_rows), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+template void filter_run<float>(chf_ham*, float*, int64_t, float*, int64_t, int, int, double, double, double,
+                                hipStream_t, int);
+template void filter_run<double>(chf_ham*, double*, int64_t, double*, int64_t, int, int, double, double, double,
+                                 hipStream_t, int);
+
 void timer_enable(int on) {
     std::lock_guard<std::mutex> lk(g_timer_mu);
     g_timer.recycle();

@@ -15,6 +15,15 @@ template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
              double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false);
 
+// Degree-m scaled Chebyshev filter in place over X and the work block W
+// (column blocks of min(nvec, ldw) vectors)
+template <class T>
+void filter_run(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b, double a0,
+                hipStream_t s, int force_kernel);
+// CHF_EINVAL unless the [n_rows][ld] spans of A and B are disjoint (capi.cpp)
+void check_disjoint(const chf_ham* H, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
+                    const char* what);
+
 // bytes of the KB coefficient scratch an H X launch on nvec vectors needs
 size_t kb_coef_bytes(const chf_ham* H, int nvec, size_t elem_bytes);
 
@@ -30,7 +39,8 @@ double dot_host(chf_ctx* ctx, int64_t n, const T* x, int64_t incx, const T* y, i
 void lincomb(int64_t n, double a, const double* x, int64_t incx, double b, const double* y, int64_t incy, double* z,
              int64_t incz, hipStream_t s);
 template <class T>
-void orthonormalize_t(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, int* fallbacks, hipStream_t s);
+void orthonormalize_t(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, bool gram64, int* fallbacks,
+                      hipStream_t s);
 template <class T>
 void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double* eig_host, T* W, int64_t ldw,
                      hipStream_t s);

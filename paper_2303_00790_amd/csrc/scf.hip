@@ -658,26 +658,10 @@ static void scf_step_t(chf_scf* S, T* X, int64_t ldx, T* W, int64_t ldw, chf_scf
         rep->bound_a = S->a;
         rep->bound_a0 = S->a0;
         rep->bound_b = b;
-        // filter: X <- p_m(H) X, in place over X and W
-        {
-            const double e = (b - S->a) / 2, c = (b + S->a) / 2;
-            const double sigma1 = e / (S->a0 - c);
-            double sigma = sigma1;
-            hx_step<T>(H, X, ldx, W, ldw, nullptr, 0, M, sigma1 / e, c, 0.0, s, 0);
-            for (int k = 2; k <= S->prm.degree; ++k) {
-                const double sn = 1.0 / (2.0 / sigma1 - sigma);
-                if (k % 2 == 0)
-                    hx_step<T>(H, W, ldw, X, ldx, X, ldx, M, 2.0 * sn / e, c, sigma * sn, s, 0);
-                else
-                    hx_step<T>(H, X, ldx, W, ldw, W, ldw, M, 2.0 * sn / e, c, sigma * sn, s, 0);
-                sigma = sn;
-            }
-            if (S->prm.degree % 2 == 1)
-                HIP_CHECK(hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), W, size_t(ldw) * sizeof(T), size_t(M) * sizeof(T),
-                                           size_t(n), hipMemcpyDeviceToDevice, s));
-        }
+        // filter: X <- p_m(H) X, in place over X and W (column blocks of W's width)
+        filter_run<T>(H, X, ldx, W, ldw, M, S->prm.degree, S->a, b, S->a0, s, 0);
         int fb = 0;
-        orthonormalize_t<T>(ctx, X, ldx, n, M, &fb, s);
+        orthonormalize_t<T>(ctx, X, ldx, n, M, S->prm.gram_dtype == CHF_F64, &fb, s);
         fb_total += fb;
         rayleigh_ritz_t<T>(H, ctx, X, ldx, M, S->eig.data(), W, ldw, s);
         S->a = S->eig[M - 1];
@@ -860,7 +844,9 @@ int chf_scf_create(chf_ham* H, chf_ctx* ctx, const chf_scf_params* prm, const do
         if (prm->degree < 1 || prm->first_iters < 1 || prm->later_iters < 1) fail(CHF_EINVAL, "chf_scf_create: bad schedule");
         if (prm->lanczos_k < 2 || prm->lanczos_k > 64) fail(CHF_EINVAL, "chf_scf_create: lanczos_k in [2, 64]");
         if (prm->filter_dtype != CHF_F32 && prm->filter_dtype != CHF_F64) fail(CHF_EINVAL, "chf_scf_create: bad filter dtype");
-        if (prm->gram_dtype != prm->filter_dtype) fail(CHF_EUNSUPPORTED, "chf_scf_create: gram dtype must equal filter dtype");
+        if (prm->gram_dtype != CHF_F32 && prm->gram_dtype != CHF_F64) fail(CHF_EINVAL, "chf_scf_create: bad Gram dtype");
+        if (prm->filter_dtype == CHF_F64 && prm->gram_dtype != CHF_F64)
+            fail(CHF_EINVAL, "chf_scf_create: an FP64 filter needs an FP64 Gram");
         if (prm->mix_history < 0 || prm->mix_history > 32 || !(prm->mix_beta > 0)) fail(CHF_EINVAL, "chf_scf_create: bad mixing");
         if (!(prm->cg_rtol > 0)) fail(CHF_EINVAL, "chf_scf_create: bad CG tolerance");
         if (!(H->dtypes & 2)) fail(CHF_EINVAL, "chf_scf_create: handle must be built with FP64");
@@ -893,7 +879,8 @@ int chf_scf_destroy(chf_scf* S) {
 int scf_step(chf_scf* S, void* X, int64_t ldx, void* W, int64_t ldw, chf_scf_report* rep, double* eig_host) {
     return scf_guard([&] {
         if (!S || !X || !W || !rep) fail(CHF_EINVAL, "scf_step: null argument");
-        if (ldx < S->prm.nvec || ldw < S->prm.nvec) fail(CHF_EINVAL, "scf_step: ld must be >= nvec");
+        if (ldx < S->prm.nvec || ldw < 1) fail(CHF_EINVAL, "scf_step: need ldx >= nvec and ldw >= 1");
+        check_disjoint(S->H, S->prm.filter_dtype, X, ldx, W, ldw, "scf_step: X and work");
         if (S->prm.filter_dtype == CHF_F64)
             scf_step_t<double>(S, static_cast<double*>(X), ldx, static_cast<double*>(W), ldw, rep, eig_host);
         else

@@ -87,6 +87,101 @@ def test_orthonormalize_f32(system):
     assert np.abs(G - np.eye(64)).max() < 5e-5
 
 
+@pytest.fixture(scope="module")
+def filtered_block(system):
+    # a block as the SCF filters it: Ritz vectors after two oracle ChFSI
+    # iterations, filtered with degree 12 between their own bounds; the
+    # columns stay nearly orthogonal but their norms spread by |T_12(t0)|, a
+    # condition number of ~1.4e2 (one FP32 Cholesky-QR pass would leave
+    # kappa^2 u_32 ~ 1e-3 of orthogonality error)
+    s = system
+    v0 = random_block(s["g"].n, 1, 3001)[:, 0]
+    b, tmin, _ = OC.lanczos_bound(s["Ho"].apply, v0)
+    a0, a = tmin, tmin + 0.1 * (b - tmin)
+    X = random_block(s["g"].n, 64, 2410)
+    for _ in range(2):
+        lam, X = OC.chfsi_iteration(s["Ho"].apply, X, 10, a, b, a0)
+        a, a0 = lam[-1], lam[0]
+    Y = OC.chebyshev_filter(s["Ho"].apply, X, 12, a, b, a0)
+    return Y / np.abs(Y).max()
+
+
+@pytest.mark.parametrize("gram_dtype", ["f32", "f64"])
+def test_orthonormalize_f32_filtered_block_matches_oracle(system, filtered_block, gram_dtype):
+    # FP32 Cholesky-QR (two passes) of a freshly filtered block against the
+    # oracle's one exact pass on the same FP32-rounded block: Q of a full-rank
+    # block is unique (positive diagonal of R), and the two-pass product of
+    # triangular factors is again such an R.  Q moves by about kappa(X) times
+    # the FP32 rounding of the block and of the updates (kappa here ~1.4e2),
+    # so 2e-4 of max |Q|; orthonormality to 1e-6; the Ritz values of the FP32
+    # Rayleigh-Ritz on the result against the oracle's within 2e-5 of the
+    # spectrum's scale (the FP32 H X and Gram products).
+    s = system
+    B = s["B"]
+    X32 = filtered_block.astype(np.float32).astype(np.float64)
+    Q, _ = OC.cholesky_qr(X32)
+    assert np.linalg.cond(X32) > 100
+    Xg = to_rows(s, X32, torch.float32)
+    fb = B.orthonormalize(s["ctx"], Xg, gram_dtype=B.CHF_F32 if gram_dtype == "f32" else B.CHF_F64)
+    assert fb == 0
+    got = from_rows(s, Xg, 64)
+    assert relerr(got, Q) < 2e-4
+    G = (Xg.double().T @ Xg.double()).cpu().numpy()
+    assert np.abs(G - np.eye(64)).max() < 1e-6
+    lam, _ = OC.rayleigh_ritz(s["Ho"].apply, Q)
+    W = torch.zeros_like(Xg)
+    eig = B.rayleigh_ritz(s["Hg"], s["ctx"], Xg, W)
+    assert np.abs(eig - lam).max() < 2e-5 * max(1.0, np.abs(lam).max())
+
+
+def test_orthonormalize_f32_retries_with_fp64_gram(system):
+    # a column dependent on the others to ~3e-4 (pivot ratio ~1e-7, below what
+    # an FP32 Gram resolves): the first pass is redone with an FP64 Gram
+    # (one retry) and the result is orthonormal and spans the same columns
+    s = system
+    B = s["B"]
+    X = random_block(s["g"].n, 32, 2411)
+    X = X / np.abs(X).max()
+    X[:, 7] = X[:, 3] + 3e-4 * X[:, 7]
+    X32 = X.astype(np.float32).astype(np.float64)
+    Xg = to_rows(s, X32, torch.float32)
+    fb = B.orthonormalize(s["ctx"], Xg)
+    assert fb == 1
+    got = from_rows(s, Xg, 32)
+    assert np.abs(got.T @ got - np.eye(32)).max() < 1e-6
+    # span: X32 = got (got^T X32)
+    assert relerr(got @ (got.T @ X32), X32) < 1e-5
+
+
+def test_orthonormalize_rejects_fp64_block_with_fp32_gram(system):
+    s = system
+    B = s["B"]
+    Xg = to_rows(s, random_block(s["g"].n, 8, 2412), torch.float64)
+    with pytest.raises(B.ChfError) as e:
+        B.orthonormalize(s["ctx"], Xg, gram_dtype=B.CHF_F32)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_rayleigh_ritz_narrow_work_matches_full_width(system, dtype, tol):
+    # W = H X in column blocks and X <- X Q in row panels through a work block
+    # of 32 columns for 64 vectors: the same result as a full-width work block
+    # up to the summation order of the products
+    s = system
+    X, _ = OC.cholesky_qr(random_block(s["g"].n, 64, 2413))
+    Xa = to_rows(s, X, dtype)
+    Xb = Xa.clone()
+    ea = s["B"].rayleigh_ritz(s["Hg"], s["ctx"], Xa, torch.zeros_like(Xa))
+    eb = s["B"].rayleigh_ritz(s["Hg"], s["ctx"], Xb, torch.zeros((s["Hg"].n_rows, 32), dtype=dtype, device="cuda"))
+    assert np.abs(ea - eb).max() < tol * np.abs(ea).max()
+    gaps = np.minimum(np.diff(ea, prepend=-np.inf), np.diff(ea, append=np.inf))
+    ok = torch.from_numpy(gaps > 1e-6).cuda()
+    da = Xa[:, ok].double()
+    db = Xb[:, ok].double()
+    sign = torch.sign((da * db).sum(0))
+    assert float((da - db * sign).abs().max() / da.abs().max()) < (1e-10 if dtype == torch.float64 else 1e-3)
+
+
 def test_orthonormalize_rank_deficient_falls_back(system):
     s = system
     X = random_block(s["g"].n, 32, 2402)

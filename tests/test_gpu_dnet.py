@@ -46,10 +46,8 @@ def from_oracle_grad(net, g):
     return flat
 
 
-@pytest.fixture(scope="module")
-def net_case():
+def _net_case(C, S):
     from paper_2303_00790_amd import binding as B
-    C, S = 8, 16
     net = B.DensityNet(C, seed=3)
     flat = net.get_params()
     rng = np.random.default_rng(9)
@@ -64,8 +62,13 @@ def net_case():
     return B, net, flat, x, t, S
 
 
-def test_forward_and_gradients(net_case):
-    B, net, flat, x, t, S = net_case
+@pytest.fixture(scope="module")
+def net_case():
+    return _net_case(8, 16)
+
+
+def _check_forward_and_gradients(case):
+    B, net, flat, x, t, S = case
     p = to_oracle(net, flat)
     y_ref, tape = U.forward(p, x[None], keep=True)
     loss_ref, dy_ref = U.mse(y_ref, t[None])
@@ -88,6 +91,20 @@ def test_forward_and_gradients(net_case):
         assert np.abs(g[sl] - ref).max() < 3e-2 * np.abs(ref).max() + 1e-12, name
         bs = slice(off[1], off[1] + cout)
         assert np.abs(g[bs] - g_ref[bs]).max() < 3e-2 * np.abs(g_ref[bs]).max() + 1e-12, name
+
+
+def test_forward_and_gradients(net_case):
+    _check_forward_and_gradients(net_case)
+
+
+def test_forward_and_gradients_trained_width():
+    # the configuration the network is trained in: 32 channels (the 64-channel
+    # concatenations of the decoder go through the multi-row-block paths of
+    # the forward, input-gradient and weight-gradient kernels) on a 32^3
+    # patch (4^3 bottleneck); every layer's weight and bias gradient is
+    # compared, which checks the input gradients of all layers after it
+    case = _net_case(32, 32)
+    _check_forward_and_gradients(case)
 
 
 def test_adam_matches_oracle(net_case):

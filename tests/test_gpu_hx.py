@@ -222,3 +222,57 @@ def test_more_atoms_per_block_than_staged():
         Yg = torch.full_like(Xg, float("nan"))
         Hg.apply(Xg, Yg, generic=generic)
         assert relerr(Yg[rows].cpu().numpy(), ref) < 1e-12
+
+
+def test_rows_with_more_than_16_projector_entries():
+    # 24 Si atoms inside 1.5 bohr of the origin: the rows near the centre have
+    # 24 projector entries (the in-march KB term takes 16 entries from the
+    # broadcast registers and the rest from memory), and every 8^3 block
+    # touches at most 24 atoms, so the coefficients are staged in LDS.
+    from paper_2303_00790_amd import binding as B
+    rng = np.random.default_rng(33)
+    d = rng.standard_normal((24, 3))
+    pos = 1.5 * d / np.linalg.norm(d, axis=1, keepdims=True) * rng.uniform(0.2, 1.0, (24, 1))
+    spc = np.zeros(24, np.int32)
+    pp = OH.PseudoParams(h_s=2.0, h_p=0.5)
+    radius = 9.0
+    g = G.build_grid(radius, H_SPACING)
+    Ho = OH.build_hamiltonian(g, pos, spc, pp)
+    Hg = B.Hamiltonian(pos, spc, pp, H_SPACING, radius, B.ORDER_HILBERT, keep_nbr=True)
+    rows = torch.from_numpy(g.row_of_rank).cuda()
+    off, rk, _ = B.projectors_host(H_SPACING, radius, pos, spc, pp)
+    per_point = np.bincount(rk, minlength=g.n)
+    assert per_point.max() == 24 and (per_point > 16).sum() > 100
+    for dtype, tol, m in ((torch.float64, 1e-12, 48), (torch.float32, 2e-6, 64)):
+        X = random_block(g.n, m, 2600 + m)
+        Xg = torch.zeros((Hg.n_rows, m), dtype=dtype, device="cuda")
+        Xg[rows] = torch.from_numpy(X).to(device="cuda", dtype=dtype)
+        ref = Ho.apply(X)
+        Yg = torch.full_like(Xg, float("nan"))
+        Hg.apply(Xg, Yg)
+        assert relerr(Yg[rows].double().cpu().numpy(), ref) < tol, dtype
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_filter_narrow_work_equals_full_width(system, dtype):
+    # a work block of 32 columns for 96 vectors: the filter runs column block
+    # by column block; every vector's arithmetic is the same as in the
+    # full-width call, so the results are identical
+    s = system
+    a, b, a0 = _bounds(s)
+    X = random_block(s["g"].n, 96, 2700)
+    Xa = to_rows(s, X, dtype)
+    Xb = Xa.clone()
+    s["Hg"].filter(Xa, torch.zeros_like(Xa), 7, a, b, a0)
+    s["Hg"].filter(Xb, torch.zeros((s["Hg"].n_rows, 32), dtype=dtype, device="cuda"), 7, a, b, a0)
+    assert torch.equal(Xa, Xb)
+
+
+def test_filter_rejects_overlapping_work(system):
+    s = system
+    B = s["B"]
+    buf = torch.zeros((s["Hg"].n_rows, 64), dtype=torch.float64, device="cuda")
+    a, b, a0 = _bounds(s)
+    with pytest.raises(B.ChfError) as e:
+        s["Hg"].filter(buf[:, :32], buf[:, 16:48], 3, a, b, a0)
+    assert e.value.code == -1

@@ -116,6 +116,57 @@ def test_scf_steps_fp64(si35):
     assert relerr(from_rows(s, rho_in), st.rho_in) < 1e-8
 
 
+def test_scf_narrow_work_matches_full_width(si35):
+    """scf_step with a work block of 32 columns for 128 states (filter in
+    column blocks, Rayleigh-Ritz rotation in row panels) gives the
+    full-width step's eigenvalues, energy and SRE within 1e-12 (FP64; the
+    two differ only in the summation order of the Gram and rotation
+    products)."""
+    s = si35
+    B = s["B"]
+    c = s["c"]
+    ne = c.n_electrons
+    M = n_states(ne)
+    X0 = random_block(s["g"].n, M, 2005)
+    v0 = to_rows(s, random_block(s["g"].n, 1, 3005)[:, 0], torch.float64)
+    eii = OS.ion_energy(c.pos, s["pp"].charges(c.species))
+    prm = B.ScfParams(ne, M, 10, 4, 1, 10, B.CHF_F64, B.CHF_F64, 6, 0.3, 1e-12, eii)
+    rho0 = s["Hg"].sad_density(c.pos, c.species, ne)
+    runs = []
+    for width in (M, 32):
+        scf = B.Scf(s["Hg"], s["ctx"], prm, rho0, v0)
+        X = to_rows(s, X0, torch.float64)
+        W = torch.zeros((s["Hg"].n_rows, width), dtype=torch.float64, device="cuda")
+        runs.append([scf.step(X, W) for _ in range(2)] + [X])
+    for k in range(2):
+        (ra, ea), (rb, eb) = runs[0][k], runs[1][k]
+        assert np.abs(ea - eb).max() < 1e-12 * np.abs(ea).max(), k
+        assert abs(ra.energy - rb.energy) < 1e-12 * abs(ra.energy), k
+        assert abs(ra.sre_ry - rb.sre_ry) < 1e-10 * ra.sre_ry, k
+    n_occ = ne // 2
+    Xa, Xb = runs[0][2][:, :n_occ], runs[1][2][:, :n_occ]
+    # occupied subspaces agree: the projectors X X^T on the occupied columns
+    overlap = (Xa.T @ Xb).cpu().numpy()
+    assert abs(np.linalg.svd(overlap, compute_uv=False).min() - 1.0) < 1e-10
+
+
+def test_scf_step_rejects_overlapping_work(si35):
+    s = si35
+    B = s["B"]
+    c = s["c"]
+    ne = c.n_electrons
+    M = n_states(ne)
+    eii = OS.ion_energy(c.pos, s["pp"].charges(c.species))
+    prm = B.ScfParams(ne, M, 10, 4, 1, 10, B.CHF_F64, B.CHF_F64, 6, 0.3, 1e-12, eii)
+    rho0 = s["Hg"].sad_density(c.pos, c.species, ne)
+    v0 = to_rows(s, random_block(s["g"].n, 1, 3005)[:, 0], torch.float64)
+    scf = B.Scf(s["Hg"], s["ctx"], prm, rho0, v0)
+    buf = torch.zeros((s["Hg"].n_rows, 2 * M), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.ChfError) as e:
+        scf.step(buf[:, :M], buf[:, M // 2:M // 2 + 32])
+    assert e.value.code == -1
+
+
 def test_checkpoint_resume_is_bit_exact(si35):
     """Saving the SCF state after three steps and resuming it in a fresh
     handle reproduces the fourth step of the uninterrupted run exactly."""

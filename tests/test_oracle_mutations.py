@@ -341,6 +341,25 @@ def sad_density_unnormalised(g, pos, species, n_electrons, alpha_si=0.074, alpha
     return rho * (n_electrons / rho.sum())                # slip: h^3 left out of the normalisation
 
 
+def _sad_with(z_si, z_h, swap, half_exponent, norm_power):
+    def sad(g, pos, species, n_electrons, alpha_si=0.074, alpha_h=0.21):
+        rho = np.zeros(g.n)
+        for a in range(len(species)):
+            si = species[a] == 0
+            al = (alpha_h if si else alpha_si) if swap else (alpha_si if si else alpha_h)
+            z = z_si if si else z_h
+            d2 = ((g.xyz - pos[a]) ** 2).sum(axis=1)
+            rho += z * (al / math.pi) ** norm_power * np.exp(-(0.5 if half_exponent else 1.0) * al * d2)
+        return rho * (n_electrons / (g.h ** 3 * rho.sum()))
+    return sad
+
+
+sad_density_widths_swapped = _sad_with(4.0, 1.0, True, False, 1.5)        # slip: alpha_Si and alpha_H exchanged
+sad_density_half_exponent = _sad_with(4.0, 1.0, False, True, 1.5)         # slip: exp(-alpha r^2 / 2)
+sad_density_norm_power_one = _sad_with(4.0, 1.0, False, False, 1.0)       # slip: (alpha / pi)^1
+sad_density_equal_charges = _sad_with(1.0, 1.0, False, False, 1.5)        # slip: Z = 1 for Si
+
+
 def solid_harmonics_unscaled_l2(x, y, z):
     R = SOLID(x, y, z).copy()
     R[4] *= 2.0                                          # slip: (3 z^2 - r^2) without its 1/2
@@ -504,6 +523,7 @@ PINS = {
     "Hilbert block layout": lambda f: TG.test_ordering_layout(G.ORDER_HILBERT),
     "LDA derivative, both branches": lambda f: TS.test_lda_energy_derivative_on_both_branches(),
     "SAD normalisation": lambda f: TS.test_sad_density_normalised(),
+    "SAD profile per species": lambda f: TS.test_sad_density_profile_per_species(),
     "addition theorem": lambda f: TS.test_solid_harmonics_addition_theorem(),
     "multipole exterior": lambda f: TS.test_multipole_potential_exterior(),
     "ghost points brute force": lambda f: TS.test_ghost_points_brute_force(),
@@ -575,6 +595,11 @@ CASES = {
     "block-local index y fastest": (G, "build_grid", build_grid_local_xy_swapped, ["Hilbert block layout"]),
     "LDA derivative branch": (S, "lda_deps_drs", lda_derivative_branch, ["LDA derivative, both branches"]),
     "SAD normalisation without h^3": (S, "sad_density", sad_density_unnormalised, ["SAD normalisation"]),
+    "SAD widths swapped between species": (S, "sad_density", sad_density_widths_swapped,
+                                           ["SAD profile per species"]),
+    "SAD Gaussian exponent halved": (S, "sad_density", sad_density_half_exponent, ["SAD profile per species"]),
+    "SAD normalisation power of alpha": (S, "sad_density", sad_density_norm_power_one, ["SAD profile per species"]),
+    "SAD Si charge 1": (S, "sad_density", sad_density_equal_charges, ["SAD profile per species"]),
     "solid harmonic l=2 scale": (S, "solid_harmonics", solid_harmonics_unscaled_l2,
                                  ["addition theorem", "multipole exterior"]),
     "multipole moments without h^3": (S, "multipole_moments", multipole_moments_without_h3,

@@ -162,6 +162,26 @@ def test_sad_density_normalised():
     assert abs(g.h ** 3 * rho.sum() - 5) < 1e-12 and (rho > 0).all()
 
 
+def test_sad_density_profile_per_species():
+    # A normalised Gaussian (alpha / pi)^(3/2) exp(-alpha r^2) carries unit
+    # charge and has <r^2> = 3 / (2 alpha).  One Si and one H, 36.4 bohr apart
+    # and 21 bohr from the wall, each sitting on a grid point: the charge on
+    # each side of the midplane is that species' Z, and its second moment
+    # about its own atom is Z * 3 / (2 alpha) for that species' alpha.  The
+    # grid sums of these smooth Gaussians are exact far below 1e-9.
+    h, a_si, a_h = 0.7, 0.074, 0.21
+    g = G.build_grid(39.2, h)
+    pos = np.array([[-18.2, 0.0, 0.0], [18.2, 0.0, 0.0]])
+    rho = S.sad_density(g, pos, np.array([0, 1], np.int32), 5, alpha_si=a_si, alpha_h=a_h)
+    left = g.xyz[:, 0] < 0
+    h3 = h ** 3
+    for side, z, alpha, centre in ((left, 4.0, a_si, pos[0]), (~left, 1.0, a_h, pos[1])):
+        q = h3 * rho[side].sum()
+        m2 = h3 * (rho[side] * ((g.xyz[side] - centre) ** 2).sum(axis=1)).sum()
+        assert abs(q - z) < 1e-9 * z, (q, z)
+        assert abs(m2 - 1.5 * z / alpha) < 1e-9 * (1.5 * z / alpha), (m2, 1.5 * z / alpha)
+
+
 def test_density_counts_two_electrons_per_occupied_state():
     # with orthonormal columns X the orbitals X_i / h^(3/2) are normalised in
     # the grid quadrature, and each occupied state holds two electrons:
