@@ -180,6 +180,25 @@ int ham_apply(chf_ham* ham, chf_dtype dtype, const void* X_dev, int64_t ldx, voi
 int chebyshev_filter(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
                      double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as chebyshev_filter, same arguments, results and errors, except
+ * that it makes no device allocation and records no kernel timers.  The KB
+ * coefficients it rewrites every degree step live in a fixed 64 MiB device
+ * array that the library holds on each device it runs on until the process
+ * ends (set up by the first ham_build on that device), instead of in the
+ * handle's scratch.  The block is filtered in column blocks of
+ * min(nvec, ldw, 64 MiB / (4 n_proj sizeof(element))) vectors, rounded down
+ * to a multiple of 64 (or of 4) when fewer than nvec.  Limit: CHF_EINVAL if
+ * the coefficients of one vector, 4 n_proj elements, exceed 64 MiB (more
+ * than 4,194,304 FP32 or 2,097,152 FP64 projector atoms).  Every call on a
+ * device shares that device's array: calls that overlap on one device (on
+ * different streams or threads) race and must be serialised by the caller.
+ * Nothing in the array needs to start at zero: each degree step overwrites
+ * the coefficients it reads. */
+int chebyshev_filter_noalloc(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
+                             double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
+
 /* The same operator and filter forced onto the neighbour-table kernel (needs
  * keep_nbr): a layout-independent second device path used to cross-check the
  * Hilbert-tiled kernel. */

@@ -78,6 +78,7 @@ _SIGS = {
     "chf_ham_apply_generic": [P, INT, P, I64, P, I64, INT, P],
     "chebyshev_filter": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
     "chf_filter_generic": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
+    "chebyshev_filter_noalloc": [P, INT, P, I64, INT, INT, D, D, D, P, I64, P],
     "lanczos_bound": [P, P, P, INT, P, P],
     "chf_timer": [INT],
     "chf_timer_read": [P, P],

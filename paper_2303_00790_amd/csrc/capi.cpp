@@ -104,10 +104,13 @@ void check_disjoint(const chf_ham* H, int dtype, const void* A, int64_t lda, con
 
 namespace chf {
 
+// force_kernel: 0 = best kernel, 1 = neighbour-table kernel, 2 = best kernel
+// with the KB coefficients in the fixed device scratch (no allocation)
 static int filter_impl(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
                        double a0, void* work, int64_t ldw, void* stream, int force_kernel) {
     return guarded([&] {
-        CHF_REQUIRE(H, force_kernel ? "chf_filter_generic: null handle" : "chebyshev_filter: null handle");
+        CHF_REQUIRE(H, force_kernel == 1 ? "chf_filter_generic: null handle"
+                       : force_kernel == 2 ? "chebyshev_filter_noalloc: null handle" : "chebyshev_filter: null handle");
         check_device(H);
         check_block(H, dtype, X, ldx, nvec, "chebyshev_filter X");
         check_block(H, dtype, work, ldw, std::min<int64_t>(nvec, ldw), "chebyshev_filter work");
@@ -116,7 +119,14 @@ static int filter_impl(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nv
         CHF_REQUIRE(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0), "chebyshev_filter: non-finite bounds");
         CHF_REQUIRE(a < b && a0 < a, "chebyshev_filter: need a0 < a < b");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        if (dtype == CHF_F64)
+        if (force_kernel == 2) {
+            if (dtype == CHF_F64)
+                filter_run_noalloc<double>(H, static_cast<double*>(X), ldx, static_cast<double*>(work), ldw, nvec, degree,
+                                           a, b, a0, s);
+            else
+                filter_run_noalloc<float>(H, static_cast<float*>(X), ldx, static_cast<float*>(work), ldw, nvec, degree, a,
+                                          b, a0, s);
+        } else if (dtype == CHF_F64)
             filter_run<double>(H, static_cast<double*>(X), ldx, static_cast<double*>(work), ldw, nvec, degree, a, b, a0,
                                s, force_kernel);
         else
@@ -152,6 +162,7 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
         hipStream_t s = static_cast<hipStream_t>(stream);
         auto H = std::make_unique<chf_ham>();
         HIP_CHECK(hipGetDevice(&H->device));
+        noalloc_scratch_init(H->device);
         H->h = gd->h;
         H->dtypes = gd->dtypes;
         H->stream = s;
@@ -402,6 +413,11 @@ int chebyshev_filter(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec
 int chf_filter_generic(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a, double b,
                        double a0, void* work, int64_t ldw, void* stream) {
     return filter_impl(H, dtype, X, ldx, nvec, degree, a, b, a0, work, ldw, stream, 1);
+}
+
+int chebyshev_filter_noalloc(chf_ham* H, chf_dtype dtype, void* X, int64_t ldx, int nvec, int degree, double a,
+                             double b, double a0, void* work, int64_t ldw, void* stream) {
+    return filter_impl(H, dtype, X, ldx, nvec, degree, a, b, a0, work, ldw, stream, 2);
 }
 
 int chf_timer(int enable) {

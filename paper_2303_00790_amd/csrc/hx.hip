@@ -901,16 +901,25 @@ size_t kb_coef_bytes(const chf_ham* H, int nvec, size_t elem_bytes) {
 
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only) {
-    H->kb_coef.ensure(kb_coef_bytes(H, nvec, sizeof(T)));
-    T* C = H->kb_coef.as<T>();
-    if (H->proj.n_proj > 0 && !lap_only) timed(1, s, [&] { launch_kb_gather<T>(H, X, ldx, nvec, C, s); });
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only, T* C_ext) {
+    // the KB coefficients go to the handle's scratch (grown on demand), or to
+    // the caller's C_ext (no allocation, no kernel timing)
+    T* C = C_ext;
+    if (!C) {
+        H->kb_coef.ensure(kb_coef_bytes(H, nvec, sizeof(T)));
+        C = H->kb_coef.as<T>();
+    }
+    auto run = [&](int which, auto&& launch) {
+        if (C_ext) launch();
+        else timed(which, s, launch);
+    };
+    if (H->proj.n_proj > 0 && !lap_only) run(1, [&] { launch_kb_gather<T>(H, X, ldx, nvec, C, s); });
     const bool tiled = force_kernel != 1 && tiled_ok<T>(H, X, ldx, Y, ldy, Z, ldz, nvec);
     if (tiled) {
-        timed(0, s, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
+        run(0, [&] { launch_hx_tiled<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
     } else {
         if (!H->has_nbr) fail(CHF_EUNSUPPORTED, "generic H X needs the neighbour table (keep_nbr) for this layout");
-        timed(0, s, [&] { launch_hx_generic<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
+        run(0, [&] { launch_hx_generic<T>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only); });
     }
 }
 
@@ -923,28 +932,30 @@ void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z,
 //   sigma_1 = e / (a0 - c), sigma_k = 1 / (2 / sigma_1 - sigma_{k-1}).
 // Y_k overwrites Y_{k-2} in place (X for even k, the work block for odd k).
 // The vectors are independent, so a work block narrower than the block is
-// used column block by column block: min(nvec, ldw) columns at a time (a
-// multiple of 64 when ldw allows, so that every block keeps the kernels'
-// vector-chunk alignment).
+// used column block by column block: min(nvec, ldw, max_cols) columns at a
+// time (a multiple of 64, else of 4, when fewer than nvec, so that every
+// block keeps the kernels' 16-byte alignment).  C_ext: KB-coefficient
+// scratch of the caller for max_cols vectors (NULL: the handle's own).
 template <class T>
 void filter_run(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b, double a0,
-                hipStream_t s, int force_kernel) {
+                hipStream_t s, int force_kernel, int64_t max_cols, T* C_ext) {
     const double e = (b - a) / 2, c = (b + a) / 2;
     const double sigma1 = e / (a0 - c);
-    int64_t nb = std::min<int64_t>(nvec, ldw);
+    int64_t nb = std::min<int64_t>(nvec, std::min<int64_t>(ldw, max_cols));
     if (nb < nvec && nb >= 64) nb -= nb % 64;
+    else if (nb < nvec && nb >= 4) nb -= nb % 4;
     for (int c0 = 0; c0 < nvec; c0 += int(nb)) {
         const int w = int(std::min<int64_t>(nb, nvec - c0));
         T* Xc = X + c0;
         double sigma = sigma1;
-        hx_step<T>(H, Xc, ldx, W, ldw, nullptr, 0, w, sigma1 / e, c, 0.0, s, force_kernel);
+        hx_step<T>(H, Xc, ldx, W, ldw, nullptr, 0, w, sigma1 / e, c, 0.0, s, force_kernel, false, C_ext);
         for (int k = 2; k <= m; ++k) {
             const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
             const double alpha = 2.0 * sigma_next / e, beta = sigma * sigma_next;
             if (k % 2 == 0)
-                hx_step<T>(H, W, ldw, Xc, ldx, Xc, ldx, w, alpha, c, beta, s, force_kernel);
+                hx_step<T>(H, W, ldw, Xc, ldx, Xc, ldx, w, alpha, c, beta, s, force_kernel, false, C_ext);
             else
-                hx_step<T>(H, Xc, ldx, W, ldw, W, ldw, w, alpha, c, beta, s, force_kernel);
+                hx_step<T>(H, Xc, ldx, W, ldw, W, ldw, w, alpha, c, beta, s, force_kernel, false, C_ext);
             sigma = sigma_next;
         }
         if (m % 2 == 1)
@@ -954,9 +965,56 @@ void filter_run(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int 
 }
 
 template void filter_run<float>(chf_ham*, float*, int64_t, float*, int64_t, int, int, double, double, double,
-                                hipStream_t, int);
+                                hipStream_t, int, int64_t, float*);
 template void filter_run<double>(chf_ham*, double*, int64_t, double*, int64_t, int, int, double, double, double,
-                                 hipStream_t, int);
+                                 hipStream_t, int, int64_t, double*);
+
+// ---------------------------------------------------------------------------
+// Allocation-free filter (chebyshev_filter_noalloc): the KB coefficients live
+// in this fixed device array instead of the handle's scratch.  Each device
+// the library runs on holds its own copy until the process ends; its address
+// on a device is looked up once, with that device current, when the first
+// Hamiltonian is built there (ham_build), and only that address is passed to
+// kernels.  Calls that overlap on one device share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+void noalloc_scratch_init(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    CHF_REQUIRE(device >= 0 && device < kMaxDevices, "device index %d beyond %d", device, kMaxDevices);
+    if (g_scratch_ptr[device]) return;
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    CHF_REQUIRE(p != nullptr, "no device address for the filter scratch");
+    g_scratch_ptr[device] = p;
+}
+
+template <class T>
+void filter_run_noalloc(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b,
+                        double a0, hipStream_t s) {
+    void* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (H->device >= 0 && H->device < kMaxDevices) p = g_scratch_ptr[H->device];
+    }
+    if (!p) fail(CHF_EINVAL, "chebyshev_filter_noalloc: no scratch on device %d (no Hamiltonian built there)", H->device);
+    // KB coefficients of one vector: 4 channels per projector atom
+    const size_t per_vec = size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * sizeof(T);
+    const int64_t max_cols = int64_t(kNoallocScratchBytes / per_vec);
+    if (max_cols < 1)
+        fail(CHF_EINVAL, "chebyshev_filter_noalloc: the KB coefficients of one vector (%zu bytes for %lld projector "
+             "atoms) exceed the %zu-byte scratch", per_vec, (long long)H->proj.n_proj, kNoallocScratchBytes);
+    filter_run<T>(H, X, ldx, W, ldw, nvec, m, a, b, a0, s, 0, max_cols, static_cast<T*>(p));
+}
+
+template void filter_run_noalloc<float>(chf_ham*, float*, int64_t, float*, int64_t, int, int, double, double, double,
+                                        hipStream_t);
+template void filter_run_noalloc<double>(chf_ham*, double*, int64_t, double*, int64_t, int, int, double, double,
+                                         double, hipStream_t);
 
 void timer_enable(int on) {
     std::lock_guard<std::mutex> lk(g_timer_mu);
@@ -980,9 +1038,9 @@ void timer_read(double* ms, int64_t* launches) {
 }
 
 template void hx_step<float>(chf_ham*, const float*, int64_t, float*, int64_t, const float*, int64_t, int, double,
-                             double, double, hipStream_t, int, bool);
+                             double, double, hipStream_t, int, bool, float*);
 template void hx_step<double>(chf_ham*, const double*, int64_t, double*, int64_t, const double*, int64_t, int,
-                              double, double, double, hipStream_t, int, bool);
+                              double, double, double, hipStream_t, int, bool, double*);
 template void launch_kb_gather<float>(chf_ham*, const float*, int64_t, int, float*, hipStream_t);
 template void launch_kb_gather<double>(chf_ham*, const double*, int64_t, int, double*, hipStream_t);
 

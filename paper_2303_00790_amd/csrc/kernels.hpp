@@ -11,15 +11,24 @@ void launch_kb_gather(chf_ham* H, const T* X, int64_t ldx, int nvec, T* C, hipSt
 // Y = alpha (H X - shift X) - beta Z ; Z may be null or alias Y.  force_kernel:
 // 0 = best available, 1 = generic neighbour-table kernel.  lap_only: H is
 // replaced by -1/2 L (no V_eff, no projectors).
+// C_ext: caller-provided KB-coefficient scratch for nvec vectors (no
+// allocation, no kernel timing); NULL uses the handle's scratch.
 template <class T>
 void hx_step(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec, double alpha,
-             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false);
+             double shift, double beta, hipStream_t s, int force_kernel, bool lap_only = false, T* C_ext = nullptr);
 
 // Degree-m scaled Chebyshev filter in place over X and the work block W
 // (column blocks of min(nvec, ldw) vectors)
 template <class T>
 void filter_run(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b, double a0,
-                hipStream_t s, int force_kernel);
+                hipStream_t s, int force_kernel, int64_t max_cols = INT64_MAX, T* C_ext = nullptr);
+// the same filter with the KB coefficients in the library's fixed device
+// scratch (no allocation); noalloc_scratch_init looks its address up for the
+// current device (called by ham_build)
+void noalloc_scratch_init(int device);
+template <class T>
+void filter_run_noalloc(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nvec, int m, double a, double b,
+                        double a0, hipStream_t s);
 // CHF_EINVAL unless the [n_rows][ld] spans of A and B are disjoint (capi.cpp)
 void check_disjoint(const chf_ham* H, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
                     const char* what);
