@@ -240,6 +240,23 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
         }
         if (gd->ordering == CHF_ORDER_HILBERT) {
             upload(H->ent_slot, H->proj.ent_slot, s);
+            // staged tile kernel: LDS offset of each entry's slot, and per block,
+            // wave quad (4 consecutive rows) and plane the quad's largest count
+            std::vector<int32_t> soff(H->proj.ent_slot.size());
+            for (size_t e = 0; e < soff.size(); ++e) soff[e] = int32_t(H->proj.ent_slot[e]) * 512;
+            upload(H->ent_soff, soff, s);
+            std::vector<uint64_t> qc(size_t(g.n_blocks) * 16, 0);
+            for (int64_t b = 0; b < g.n_blocks; ++b)
+                for (int q = 0; q < 16; ++q)
+                    for (int z = 0; z < 8; ++z) {
+                        int64_t mx = 0;
+                        for (int i = 0; i < 4; ++i) {
+                            const int64_t r = b * kBlockPts + 64 * z + 4 * q + i;
+                            mx = std::max<int64_t>(mx, P.ent_off[size_t(r) + 1] - P.ent_off[size_t(r)]);
+                        }
+                        qc[size_t(b * 16 + q)] |= uint64_t(std::min<int64_t>(mx, 255)) << (8 * z);
+                    }
+            upload(H->quad_count, qc, s);
             std::vector<int32_t> off32(H->proj.blk_atom_off.begin(), H->proj.blk_atom_off.end());
             upload(H->blk_atom_off, off32, s);
             std::vector<int32_t> ba(H->proj.blk_atoms.size());

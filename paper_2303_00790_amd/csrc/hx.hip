@@ -797,6 +797,412 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Staged tile kernel: the Hilbert-blocked H X + recurrence with the KB term
+// applied inside the z-march from coefficients staged in LDS (blocks touched
+// by at most kMaxBlockAtoms projector atoms).  Same tile shape as above: one
+// workgroup per (8^3 block, 128-byte vector chunk), 1024 threads = 64
+// columns x 16 lanes of 8 bytes; a wave holds 4 columns of one row of the
+// block's plane, i.e. one aligned quad of 4 consecutive grid rows.
+//
+// The KB term of row r is sum_e h_l beta_lm(e) C_lm[slot(e)].  Lane i of a
+// column holds entry i of its row (LDS byte offset of the slot's staged
+// coefficients and h_l beta_lm), loaded two planes ahead; the wave walks the
+// entries up to the largest count among its quad's 4 rows (a per-block table
+// gives that count per quad and plane, so the loop bound is wave-uniform and
+// the loop needs no per-lane tests); lanes past their row's count hold zero
+// weights and add exact zeros.  Per pair of entries: one DPP add per entry
+// forms the LDS address (broadcast offset + lane base), two 16-byte LDS reads
+// fetch the coefficients, and FMAs with a DPP broadcast operand (row_newbcast
+// of the 16-lane group) apply them (FP64: one entry at a time, which keeps
+// the kernel within 128 registers).  Every DPP sequence starts with s_nop 1,
+// and an accumulator is written at most once every four FMAs, so no DPP
+// operand is read within two instructions of the VALU write that made it.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ inline void bcast_add2(int v, int add, int& r0, int& r1) {
+    asm("s_nop 1\n\t"
+        "v_add_u32_dpp %0, %2, %3 row_newbcast:%4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_u32_dpp %1, %2, %3 row_newbcast:%5 row_mask:0xf bank_mask:0xf"
+        : "=&v"(r0), "=&v"(r1)
+        : "v"(v), "v"(add), "n"(K), "n"(K + 1));
+}
+
+// a0..a3 += entry K and K+1 of (b0..b3) times the staged coefficients
+// ca = {ch0 v0, ch0 v1, ch1 v0, ch1 v1}, cb = {ch2 v0, ch2 v1, ch3 v0, ch3 v1}
+template <int K>
+__device__ inline void kb_fma2(float& a0, float& a1, float& a2, float& a3, float b0, float b1, float b2, float b3,
+                               float4 ca, float4 cb, float4 da, float4 db) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %4, %8 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %9 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %5, %10 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %5, %11 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %6, %12 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %6, %13 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %7, %14 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %7, %15 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %16 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %17 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %5, %18 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %5, %19 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %6, %20 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %6, %21 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %7, %22 row_newbcast:%25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %7, %23 row_newbcast:%25 row_mask:0xf bank_mask:0xf"
+        : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+        : "v"(b0), "v"(b1), "v"(b2), "v"(b3), "v"(ca.x), "v"(ca.y), "v"(ca.z), "v"(ca.w), "v"(cb.x), "v"(cb.y),
+          "v"(cb.z), "v"(cb.w), "v"(da.x), "v"(da.y), "v"(da.z), "v"(da.w), "v"(db.x), "v"(db.y), "v"(db.z),
+          "v"(db.w), "n"(K), "n"(K + 1));
+}
+
+// FP64, one entry: a0..a3 += entry K of (b0..b3) times ca = {ch0, ch1}, cb = {ch2, ch3}
+template <int K>
+__device__ inline void kb_fma1(double& a0, double& a1, double& a2, double& a3, double b0, double b1, double b2,
+                               double b3, double2 ca, double2 cb) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, %6, %10 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, %7, %11 row_newbcast:%12 row_mask:0xf bank_mask:0xf"
+        : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+        : "v"(b0), "v"(b1), "v"(b2), "v"(b3), "v"(ca.x), "v"(ca.y), "v"(cb.x), "v"(cb.y), "n"(K));
+}
+
+template <int K>
+__device__ inline int bcast_add1(int v, int add) {
+    int r;
+    asm("s_nop 1\n\t"
+        "v_add_u32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "=v"(r)
+        : "v"(v), "v"(add), "n"(K));
+    return r;
+}
+
+template <class T>
+struct KbLds;
+template <>
+struct KbLds<float> {
+    using C = float4;   // coefficients of one channel pair for the lane's 2 vectors
+};
+template <>
+struct KbLds<double> {
+    using C = double2;  // one channel pair for the lane's vector
+};
+
+template <class V>
+__device__ inline V bload_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, int(soff), 0));
+}
+// streaming access (non-temporal cache policy): Y_{k-1} is read and Y_{k+1}
+// written once per launch, so they should not displace the X rows that
+// neighbouring tiles read again as halos
+template <class V>
+__device__ inline V bload_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, int(soff), 2));
+}
+template <class V>
+__device__ inline void bstore_nt(V v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, int(soff), 2);
+}
+
+// LDS of the staged tile kernel: staged KB coefficients first (their
+// addresses fit the 16-bit offset field of the LDS instructions), then the
+// two x/y planes
+constexpr int kCstBytes = kMaxBlockAtoms * 2 * 16 * 2 * 8;      // [slot][pair][lane][2] x 8 B
+constexpr int kPlaneBytes = 2 * 400 * 16 * 8;                   // [2][400][lane] x 8 B
+constexpr int kSlotBytes = 2 * 16 * 2 * 8;                      // one slot: 512 B
+
+template <class T>
+__global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
+                                                       const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
+                                                       const int32_t* __restrict__ ent_off,
+                                                       const int32_t* __restrict__ ent_soff,
+                                                       const T* __restrict__ ent_beta,
+                                                       const uint64_t* __restrict__ qcnt,
+                                                       const int32_t* __restrict__ blk_atom_off,
+                                                       const int32_t* __restrict__ blk_atoms, const T* __restrict__ C,
+                                                       int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
+                                                       int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
+    using V = typename Lane<T>::V;
+    using CL = typename KbLds<T>::C;
+    constexpr int LANES = 16;
+    constexpr int LN = Lane<T>::N;
+    constexpr int CH = LANES * LN;
+    constexpr int NT = 64 * LANES;
+    constexpr int LSH = 4;
+    constexpr int CPW = 4;
+    __shared__ __align__(16) char lds[kCstBytes + kPlaneBytes];
+    V (*plane)[400][LANES] = reinterpret_cast<V (*)[400][LANES]>(lds + kCstBytes);
+    V (*cst)[2][LANES][2] = reinterpret_cast<V (*)[2][LANES][2]>(lds);
+
+    const int64_t ntiles = n_blocks * n_chunks;
+    const int64_t per_xcd = (ntiles + 7) / 8;
+    const int64_t tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tile >= ntiles) return;
+
+    const int t = threadIdx.x;
+    const int p = t & (LANES - 1);
+    const int col = t >> LSH;
+    const int cx = col & 7, cy = col >> 3;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const unsigned es = sizeof(T);
+    const unsigned blk_bytes = unsigned(kBlockPts) * unsigned(ldx) * es;
+    constexpr unsigned kOOB = 0x80000000u;
+    const unsigned plane_x = 64u * unsigned(ldx) * es;
+    const unsigned plane_z = 64u * unsigned(ldz) * es;
+    const unsigned plane_y = 64u * unsigned(ldy) * es;
+    const int ctr = (cy + 6) * 20 + (cx + 6);
+    auto res_x = [&](int32_t nb) {
+        return make_rsrc(nb >= 0 ? X + int64_t(nb) * kBlockPts * ldx : X, nb >= 0 ? blk_bytes : 0u);
+    };
+
+    const int64_t blk = tile / n_chunks;
+    const int chunk = int(tile - blk * n_chunks);
+    int32_t nbs[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) nbs[f] = bnb[6 * blk + f];
+    const int vbase = chunk * CH + p * LN;
+    const bool vok = vbase < nvec;
+    const unsigned off_x = vok ? (unsigned(cx + 8 * cy) * unsigned(ldx) + unsigned(vbase)) * es : kOOB;
+    const unsigned off_z = vok ? (unsigned(cx + 8 * cy) * unsigned(ldz) + unsigned(vbase)) * es : kOOB;
+    const __amdgpu_buffer_rsrc_t rOwn = res_x(int32_t(blk));
+    const __amdgpu_buffer_rsrc_t rZm = res_x(nbs[4]);
+    const __amdgpu_buffer_rsrc_t rZp = res_x(nbs[5]);
+    const __amdgpu_buffer_rsrc_t rZ =
+        make_rsrc(Z ? Z + blk * kBlockPts * ldz : X, Z ? unsigned(kBlockPts) * unsigned(ldz) * es : 0u);
+    // halo slot u of a wave covers CPW consecutive halo rows, all on one side
+    int hrow[3];
+    __amdgpu_buffer_rsrc_t rH[3];
+    unsigned hoff[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int hr0 = CPW * wave + 64 * u;
+        const int side = __builtin_amdgcn_readfirstlane(hr0 / 48);
+        const int hr = col + 64 * u;
+        const int rem = hr - 48 * side;
+        int lx, ly, x, y, nb;
+        if (side < 2) {
+            const int c6 = rem % 6;
+            ly = rem / 6;
+            lx = side == 0 ? 2 + c6 : c6;
+            x = side == 0 ? c6 - 6 : 8 + c6;
+            y = ly;
+            nb = side == 0 ? nbs[0] : nbs[1];
+        } else {
+            const int r6 = rem / 8;
+            lx = rem % 8;
+            ly = side == 2 ? 2 + r6 : r6;
+            x = lx;
+            y = side == 2 ? r6 - 6 : 8 + r6;
+            nb = side == 2 ? nbs[2] : nbs[3];
+        }
+        hrow[u] = (y + 6) * 20 + (x + 6);
+        rH[u] = res_x(__builtin_amdgcn_readfirstlane(nb));
+        hoff[u] = vok ? (unsigned(lx + 8 * ly) * unsigned(ldx) + unsigned(vbase)) * es : kOOB;
+    }
+    auto load_plane = [&](int zz) -> V {
+        if (zz < 0) return bload_s<V>(rZm, off_x, unsigned(zz + 8) * plane_x);
+        if (zz >= 8) return bload_s<V>(rZp, off_x, unsigned(zz - 8) * plane_x);
+        return bload_s<V>(rOwn, off_x, unsigned(zz) * plane_x);
+    };
+    auto load_halo = [&](int z, V* hv) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) hv[u] = bload_s<V>(rH[u], hoff[u], unsigned(z) * plane_x);
+    };
+    auto store_halo = [&](int b, const V* hv) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) plane[b][hrow[u]][p] = hv[u];
+    };
+
+    const int64_t base = blk * kBlockPts;
+    const int lrow = cx + 8 * cy;
+    // KB entries of the block: a buffer over its entries, so that lanes past
+    // their row's count read zeros (out-of-range buffer loads return 0)
+    const int e_blk0 = ent_off[base];
+    const int e_cnt = ent_off[base + kBlockPts] - e_blk0;
+    const uint64_t qc8 = qcnt[blk * 16 + wave];
+    V cstage[4];
+    {
+        const int a0 = blk_atom_off[blk];
+        const int na = min(blk_atom_off[blk + 1] - a0, kMaxBlockAtoms);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + NT * u;         // (atom slot, lm, lane)
+            const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
+            const int vb = chunk * CH + lp * LN;
+            if (sl < na && vb < nvec)         // staged with alpha applied
+                cstage[u] = lscale(k.alpha, *reinterpret_cast<const V*>(C + (int64_t(blk_atoms[a0 + sl]) * 4 + lm) * nvec + vb));
+            else
+                cstage[u] = lz<V>();
+        }
+    }
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(ent_beta + 4 * int64_t(e_blk0), unsigned(e_cnt) * 4u * es);
+    const __amdgpu_buffer_rsrc_t rS = make_rsrc(ent_soff + e_blk0, unsigned(e_cnt) * 4u);
+    // entries of row z: lane i holds entry i (LDS byte offset of its slot's
+    // coefficients and its 4 weights); the row's entry range comes 2 planes
+    // before the entries, which come PD planes before their use (1 for FP64,
+    // whose 4 weights take twice the registers)
+    constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+    int2 e_rng[8];
+    int e_soff[8];
+    T e_b[8][4];
+    // (a dword-aligned 8-byte load: the row's first entry and the next row's)
+    auto load_range = [&](int z) { __builtin_memcpy(&e_rng[z], ent_off + base + lrow + 64 * z, sizeof(int2)); };
+    auto load_entries = [&](int z) {
+        const int en = e_rng[z].x + p;
+        const unsigned rel = unsigned(en - e_blk0);
+        const bool ok = en < e_rng[z].y;
+        e_soff[z] = int(__builtin_amdgcn_raw_buffer_load_b32(rS, ok ? rel * 4u : kOOB, 0, 0));
+        if constexpr (sizeof(T) == 4) {
+            const float4 b4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? rel * 16u : kOOB, 0, 0));
+            e_b[z][0] = b4.x, e_b[z][1] = b4.y, e_b[z][2] = b4.z, e_b[z][3] = b4.w;
+        } else {
+            const unsigned o = ok ? rel * 32u : kOOB;
+            const double2 b0 = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rB, o, 0, 0));
+            const double2 b1 = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rB, o, 16, 0));
+            e_b[z][0] = b0.x, e_b[z][1] = b0.y, e_b[z][2] = b1.x, e_b[z][3] = b1.y;
+        }
+    };
+#pragma unroll
+    for (int z = 0; z < PD + 2; ++z) load_range(z);
+    // the X window of this column, the first two halo planes, Y_{k-1} and
+    // V_eff of plane 0
+    V w[20];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) w[i] = load_plane(i - 6);
+    V hv0[3], hv[3];
+    load_halo(0, hv0);
+    load_halo(1, hv);
+    V zcur = bload_nt<V>(rZ, off_z, 0u);      // zero when there is no Z (empty buffer)
+    T vcur = veff[base + lrow];
+#pragma unroll
+    for (int z = 0; z < PD; ++z) load_entries(z);
+    store_halo(0, hv0);
+    plane[0][ctr][p] = w[6];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = t + NT * u;
+        const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
+        if (sl < kMaxBlockAtoms) cst[sl][lm >> 1][lp][lm & 1] = cstage[u];
+    }
+    __syncthreads();
+
+    const __amdgpu_buffer_rsrc_t rY = make_rsrc(Y + base * ldy, unsigned(kBlockPts) * unsigned(ldy) * es);
+    const unsigned off_y = vok ? (unsigned(lrow) * unsigned(ldy) + unsigned(vbase)) * es : kOOB;
+    const int lane_off = p * 16;           // this lane's 16 bytes within a slot's channel pair
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const int b = z & 1;
+        if (z < 7) {
+            store_halo(b ^ 1, hv);
+            plane[b ^ 1][ctr][p] = w[z + 7];
+        }
+        // loads, in the order they are needed: next plane's halos, Y_{k-1}
+        // and V_eff first, then the entries of plane z + PD, the entry range
+        // of plane z + PD + 2 and the X plane z + 8
+        if (z < 6) load_halo(z + 2, hv);
+        V znext = lz<V>();
+        T vnext = T(0);
+        if (z < 7) {
+            znext = bload_nt<V>(rZ, off_z, unsigned(z + 1) * plane_z);
+            vnext = veff[base + lrow + 64 * (z + 1)];
+        }
+        if (z + PD < 8) load_entries(z + PD);
+        if (z + PD + 2 < 8) load_range(z + PD + 2);
+        if (z < 6) w[z + 14] = load_plane(z + 8);
+
+        // alpha-scaled off-diagonal stencil; the diagonal is added last
+        V acc = lz<V>();
+#pragma unroll
+        for (int s = 1; s <= 6; ++s) {
+            V sum = ladd(w[z + 6 - s], w[z + 6 + s]);
+            sum = ladd(sum, plane[b][ctr - s][p]);
+            sum = ladd(sum, plane[b][ctr + s][p]);
+            sum = ladd(sum, plane[b][ctr - 20 * s][p]);
+            sum = ladd(sum, plane[b][ctr + 20 * s][p]);
+            acc = s == 1 ? lscale(k.ac[1], sum) : lfma(k.ac[s], sum, acc);
+        }
+        const V xc = w[z + 6];
+        {
+            // KB term of row z: entries in pairs up to the quad's largest count
+            const int qc = int((qc8 >> (8 * z)) & 0xffu);
+            T a[4];
+            if constexpr (sizeof(T) == 4) {
+                a[0] = acc.x, a[1] = acc.y, a[2] = 0.f, a[3] = 0.f;
+            } else {
+                a[0] = acc, a[1] = 0.0, a[2] = 0.0, a[3] = 0.0;
+            }
+            if constexpr (sizeof(T) == 4) {
+                static_for<0, 8>([&](auto gc) {
+                    constexpr int kk = 2 * decltype(gc)::value;
+                    if (kk < qc) {
+                        int ad0, ad1;
+                        bcast_add2<kk>(e_soff[z], lane_off, ad0, ad1);
+                        const CL ca = *reinterpret_cast<const CL*>(lds + ad0);
+                        const CL cb = *reinterpret_cast<const CL*>(lds + ad0 + 256);
+                        const CL da = *reinterpret_cast<const CL*>(lds + ad1);
+                        const CL db = *reinterpret_cast<const CL*>(lds + ad1 + 256);
+                        kb_fma2<kk>(a[0], a[1], a[2], a[3], e_b[z][0], e_b[z][1], e_b[z][2], e_b[z][3], ca, cb, da,
+                                    db);
+                    }
+                });
+            } else {
+                static_for<0, 16>([&](auto kc) {
+                    constexpr int kk = decltype(kc)::value;
+                    if (kk < qc) {
+                        const int ad = bcast_add1<kk>(e_soff[z], lane_off);
+                        const CL ca = *reinterpret_cast<const CL*>(lds + ad);
+                        const CL cb = *reinterpret_cast<const CL*>(lds + ad + 256);
+                        kb_fma1<kk>(a[0], a[1], a[2], a[3], e_b[z][0], e_b[z][1], e_b[z][2], e_b[z][3], ca, cb);
+                    }
+                });
+            }
+            if (qc > 16) {                    // rows with more than 16 entries: the rest from memory
+                int2 rng;
+                __builtin_memcpy(&rng, ent_off + base + lrow + 64 * z, sizeof(int2));
+                for (int en = rng.x + 16; en < rng.y; ++en) {
+                    const T* bb = ent_beta + 4 * int64_t(en);
+                    const char* cs = lds + ent_soff[en] + lane_off;
+                    const CL c01 = *reinterpret_cast<const CL*>(cs);
+                    const CL c23 = *reinterpret_cast<const CL*>(cs + 256);
+                    if constexpr (sizeof(T) == 4) {
+                        a[0] = fmaf(bb[0], c01.x, a[0]);
+                        a[1] = fmaf(bb[0], c01.y, a[1]);
+                        a[2] = fmaf(bb[1], c01.z, a[2]);
+                        a[3] = fmaf(bb[1], c01.w, a[3]);
+                        a[0] = fmaf(bb[2], c23.x, a[0]);
+                        a[1] = fmaf(bb[2], c23.y, a[1]);
+                        a[2] = fmaf(bb[3], c23.z, a[2]);
+                        a[3] = fmaf(bb[3], c23.w, a[3]);
+                    } else {
+                        a[0] = fma(bb[0], c01.x, a[0]);
+                        a[1] = fma(bb[1], c01.y, a[1]);
+                        a[2] = fma(bb[2], c23.x, a[2]);
+                        a[3] = fma(bb[3], c23.y, a[3]);
+                    }
+                }
+            }
+            if constexpr (sizeof(T) == 4)
+                acc = make_float2(a[0] + a[2], a[1] + a[3]);
+            else
+                acc = (a[0] + a[1]) + (a[2] + a[3]);
+        }
+        const T dg = T(fma(k.alpha, vcur, k.d0));
+        V y = lfma(dg, xc, acc);
+        y = lfma(-k.beta, zcur, y);            // beta = 0 when there is no Z
+        // rows outside the sphere are stored as zero: the wave's quad is rows
+        // 4 wave .. 4 wave + 3 of the plane, 16 lanes each
+        const uint64_t m4 = (bmask[8 * blk + z] >> (4 * wave)) & 0xfu;
+        const uint64_t spread = (m4 & 1u) | ((m4 & 2u) << 15) | ((m4 & 4u) << 30) | ((m4 & 8u) << 45);
+        const bool in = __builtin_amdgcn_inverse_ballot_w64(spread * 0xffffu);
+        bstore_nt<V>(in ? y : lz<V>(), rY, off_y, unsigned(z) * plane_y);
+        zcur = znext;
+        vcur = vnext;
+        __syncthreads();
+    }
+}
+
 constexpr int kLanes = 16;
 
 template <class T, int LANES>
@@ -816,7 +1222,13 @@ static void launch_hx_tiled_l(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t
     H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,                \
         H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),     \
         H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef
-    if (stage)
+    if (stage && LANES == 16)
+        hx_tile_kernel<T><<<grid, block, 0, s>>>(H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(),
+                                                H->block_mask.as<uint64_t>(), veff, eo, H->ent_soff.as<int32_t>(),
+                                                ent_beta_of<T>(H), H->quad_count.as<uint64_t>(),
+                                                H->blk_atom_off.as<int32_t>(), H->blk_atoms.as<int32_t>(), C, nvec, X,
+                                                ldx, Y, ldy, Z, ldz, coef);
+    else if (stage)
         hx_tiled_kernel<T, true, LANES><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
     else
         hx_tiled_kernel<T, false, LANES><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
@@ -895,6 +1307,7 @@ bool tiled_ok(const chf_ham* H, const void* X, int64_t ldx, const void* Y, int64
     return true;
 }
 
+// bytes of the KB coefficient scratch C [4 n_proj][nvec] of an H X launch
 size_t kb_coef_bytes(const chf_ham* H, int nvec, size_t elem_bytes) {
     return size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * size_t(nvec) * elem_bytes;
 }
@@ -1003,7 +1416,7 @@ void filter_run_noalloc(chf_ham* H, T* X, int64_t ldx, T* W, int64_t ldw, int nv
     }
     if (!p) fail(CHF_EINVAL, "chebyshev_filter_noalloc: no scratch on device %d (no Hamiltonian built there)", H->device);
     // KB coefficients of one vector: 4 channels per projector atom
-    const size_t per_vec = size_t(std::max<int64_t>(1, H->proj.n_proj)) * 4 * sizeof(T);
+    const size_t per_vec = kb_coef_bytes(H, 1, sizeof(T));
     const int64_t max_cols = int64_t(kNoallocScratchBytes / per_vec);
     if (max_cols < 1)
         fail(CHF_EINVAL, "chebyshev_filter_noalloc: the KB coefficients of one vector (%zu bytes for %lld projector "
