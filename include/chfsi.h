@@ -446,9 +446,12 @@ int dnet_crop(const float* box_dev, int D, int S, int ox, int oy, int oz, int sy
 int dnet_highpass(const float* box_dev, int D, double sigma, float* out_dev, float* work_dev, void* stream);
 
 /* Grid rows <-> cubic box of edge D (x-fastest) holding grid point (i, j, k)
- * at (i + off, j + off, k + off): box = scale * rows (cells without a grid
- * point 0); rows_out = base_rows + box / scale on inside rows (padding 0). */
-int chf_rows_to_box(chf_ham* ham, const double* rows_dev, double scale, float* box_dev, int D, int off, void* stream);
+ * at (i + off, j + off, k + off): box = scale * (rows - base_rows), the
+ * difference taken in FP64 (base_rows_dev may be NULL: 0; cells without a
+ * grid point 0); rows_out = base_rows + box / scale on inside rows (padding
+ * 0; base_rows_dev may be NULL). */
+int chf_rows_to_box(chf_ham* ham, const double* rows_dev, const double* base_rows_dev, double scale, float* box_dev,
+                    int D, int off, void* stream);
 int chf_box_to_rows(chf_ham* ham, const float* box_dev, int D, int off, double scale, const double* base_rows_dev,
                     double* rows_out_dev, void* stream);
 

@@ -114,7 +114,7 @@ _SIGS = {
     "dnet_mse": [P, P, P, I64, C.POINTER(D), P, P],
     "dnet_crop": [P, INT, INT, INT, INT, INT, INT, P, P],
     "dnet_highpass": [P, INT, D, P, P, P],
-    "chf_rows_to_box": [P, P, D, P, INT, INT, P],
+    "chf_rows_to_box": [P, P, P, D, P, INT, INT, P],
     "chf_box_to_rows": [P, P, INT, INT, D, P, P, P],
 }
 
@@ -567,8 +567,10 @@ def highpass(box, D: int, sigma: float, out, work) -> None:
          _vec(out, D ** 3, "out", double=False), _vec(work, 2 * D ** 3, "work", double=False), _stream())
 
 
-def rows_to_box(H: "Hamiltonian", rows, scale: float, box, D: int, off: int) -> None:
-    call("chf_rows_to_box", H.handle, _vec(rows, H.n_rows, "rows"), scale, _vec(box, D ** 3, "box", double=False), D,
+def rows_to_box(H: "Hamiltonian", rows, scale: float, box, D: int, off: int, base=None) -> None:
+    """box = scale * (rows - base) on the cells of the grid points (base None: 0)."""
+    call("chf_rows_to_box", H.handle, _vec(rows, H.n_rows, "rows"),
+         _vec(base, H.n_rows, "base") if base is not None else None, scale, _vec(box, D ** 3, "box", double=False), D,
          off, _stream())
 
 

@@ -128,18 +128,19 @@ static double tridiag_eig(const std::vector<double>& d, const std::vector<double
 // ---------------------------------------------------------------------------
 // Gram products S = A^T B
 // ---------------------------------------------------------------------------
-// S[i][j] = sum over row slices of part[s][i][j], in FP64 and in slice order;
-// with a symmetric product only i <= j is summed and mirrored, so S is
-// exactly symmetric.
+// S[i][j] (+)= sum over row slices of part[s][i][j], in FP64 and in slice
+// order (accumulate: add to S, for the slice groups after the first); with a
+// symmetric product only i <= j is summed and mirrored, so S is exactly
+// symmetric.
 template <class P>
 __global__ void gram_slices_reduce_kernel(int m, int n, int n_slices, const P* __restrict__ part,
-                                          double* __restrict__ S, int64_t lds, int symmetric) {
+                                          double* __restrict__ S, int64_t lds, int symmetric, int accumulate) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= int64_t(m) * n) return;
     const int i = int(idx / n), j = int(idx % n);
     if (symmetric && i > j) return;
     const int64_t stride = int64_t(m) * n;
-    double acc = 0.0;
+    double acc = accumulate ? S[int64_t(i) * lds + j] : 0.0;
     for (int k = 0; k < n_slices; ++k) acc += double(part[k * stride + idx]);
     S[int64_t(i) * lds + j] = acc;
     if (symmetric && i < j) S[int64_t(j) * lds + i] = acc;
@@ -161,30 +162,38 @@ static rocblas_status gemm_sb(rocblas_handle h, rocblas_int M, rocblas_int N, ro
 }
 
 // Gram S = A^T B over n_rows rows.  X^T X is a plain GEMM, so the products of
-// row slices run as one strided-batched rocBLAS GEMM (MFMA, accumulating in
-// the block precision within a slice) into partials that are summed in FP64.
-// Slices: at least kGramMinSliceRows rows, at most kGramMaxSlices of them and
-// kGramPartBytes of partials.
+// row slices run as strided-batched rocBLAS GEMMs (MFMA, accumulating in the
+// block precision within a slice) into partials that are summed in FP64.
+// Slices: at least kGramMinSliceRows rows, at most kGramMaxSlices per batch,
+// and every GEMM operand spans fewer than kBlasMaxElems elements (the BLAS
+// calls take 32-bit sizes and offsets); the slices run in groups whose
+// partials fit kGramPartBytes, each group's sum added to S in slice order.
 constexpr int64_t kGramMinSliceRows = 4096;
 constexpr int64_t kGramMaxSlices = 256;
 constexpr size_t kGramPartBytes = size_t(1) << 30;
+constexpr int64_t kBlasMaxElems = (int64_t(1) << 31) - (int64_t(1) << 20);
 
 struct GramSlices {
     int64_t rows;      // rows per slice
     int64_t full;      // slices of exactly `rows` rows
     int64_t tail;      // rows of the last, shorter slice (0: none)
+    int64_t group;     // slices per batched GEMM (their partials at once)
     size_t part_bytes; // partials scratch
 };
 
-static GramSlices gram_slices(int64_t n_rows, int m, int n, size_t elem_bytes) {
+static GramSlices gram_slices(int64_t n_rows, int m, int n, size_t elem_bytes, int64_t ld) {
     const size_t per = size_t(m) * size_t(n) * elem_bytes;
     int64_t ns = std::min<int64_t>(kGramMaxSlices, std::max<int64_t>(1, n_rows / kGramMinSliceRows));
-    ns = std::max<int64_t>(1, std::min<int64_t>(ns, int64_t(kGramPartBytes / std::max<size_t>(1, per))));
+    const int64_t max_group = std::max<int64_t>(1, int64_t(kGramPartBytes / std::max<size_t>(1, per)));
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, max_group));
     GramSlices g;
     g.rows = std::max<int64_t>(1, (n_rows + ns - 1) / ns);
+    g.rows = std::min<int64_t>(g.rows, std::max<int64_t>(1, kBlasMaxElems / std::max<int64_t>(1, ld)));
     g.full = n_rows / g.rows;
     g.tail = n_rows - g.full * g.rows;
-    g.part_bytes = size_t(std::max<int64_t>(1, g.full + (g.tail > 0 ? 1 : 0))) * per;
+    const int64_t total = g.full + (g.tail > 0 ? 1 : 0);
+    g.group = std::max<int64_t>(1, std::min<int64_t>(total, max_group));
+    g.part_bytes = size_t(std::max<int64_t>(1, g.group)) * per;
     return g;
 }
 
@@ -193,27 +202,38 @@ void gram_product(chf_ctx* ctx, const T* A, int64_t lda, const T* B, int64_t ldb
                   double* S, int64_t lds, hipStream_t s) {
     const bool symmetric = (A == B) && (m == n) && (lda == ldb);
     const size_t per = size_t(m) * size_t(n) * sizeof(T);
-    const GramSlices g = gram_slices(n_rows, m, n, sizeof(T));
-    const int64_t R = g.rows, nf = g.full, tail = g.tail;
-    const int64_t n_slices = nf + (tail > 0 ? 1 : 0);
+    const GramSlices g = gram_slices(n_rows, m, n, sizeof(T), std::max(lda, ldb));
+    const int64_t R = g.rows;
+    const int64_t n_slices = g.full + (g.tail > 0 ? 1 : 0);
     CHF_REQUIRE(R <= INT32_MAX && lda <= INT32_MAX && ldb <= INT32_MAX, "gram: dimensions beyond 32-bit BLAS");
     ctx->scratch2.ensure(g.part_bytes);
     T* part = ctx->scratch2.as<T>();
     ROCBLAS_CHECK(rocblas_set_stream(ctx->blas, s));
-    // column-major view: part_s (n x m, ld n) = B_s (n x R, ld ldb) * A_s^T
-    if (nf > 0)
-        ROCBLAS_CHECK(gemm_sb(ctx->blas, n, m, rocblas_int(R), B, rocblas_int(ldb), R * ldb, A, rocblas_int(lda),
-                              R * lda, part, n, int64_t(m) * n, rocblas_int(nf)));
-    if (tail > 0)
-        ROCBLAS_CHECK(gemm_sb(ctx->blas, n, m, rocblas_int(tail), B + nf * R * ldb, rocblas_int(ldb), 0,
-                              A + nf * R * lda, rocblas_int(lda), 0, part + nf * int64_t(m) * n, n, 0, 1));
+    const int64_t tot = int64_t(m) * n;
     if (n_slices == 0) {
         HIP_CHECK(hipMemsetAsync(part, 0, per, s));
+        gram_slices_reduce_kernel<T><<<unsigned((tot + 255) / 256), 256, 0, s>>>(m, n, 1, part, S, lds,
+                                                                                symmetric ? 1 : 0, 0);
+        LAUNCH_CHECK();
+        return;
     }
-    const int64_t tot = int64_t(m) * n;
-    gram_slices_reduce_kernel<T><<<unsigned((tot + 255) / 256), 256, 0, s>>>(
-        m, n, int(std::max<int64_t>(1, n_slices)), part, S, lds, symmetric ? 1 : 0);
-    LAUNCH_CHECK();
+    for (int64_t s0 = 0; s0 < n_slices; s0 += g.group) {
+        const int64_t cnt = std::min<int64_t>(g.group, n_slices - s0);
+        // full slices of this group, then (in the last group) the tail
+        const int64_t nfull = std::max<int64_t>(0, std::min<int64_t>(cnt, g.full - s0));
+        const T* A0 = A + s0 * R * lda;
+        const T* B0 = B + s0 * R * ldb;
+        // column-major view: part_k (n x m, ld n) = B_k (n x R, ld ldb) * A_k^T
+        if (nfull > 0)
+            ROCBLAS_CHECK(gemm_sb(ctx->blas, n, m, rocblas_int(R), B0, rocblas_int(ldb), R * ldb, A0,
+                                  rocblas_int(lda), R * lda, part, n, int64_t(m) * n, rocblas_int(nfull)));
+        if (nfull < cnt)
+            ROCBLAS_CHECK(gemm_sb(ctx->blas, n, m, rocblas_int(g.tail), B0 + nfull * R * ldb, rocblas_int(ldb), 0,
+                                  A0 + nfull * R * lda, rocblas_int(lda), 0, part + nfull * int64_t(m) * n, n, 0, 1));
+        gram_slices_reduce_kernel<T><<<unsigned((tot + 255) / 256), 256, 0, s>>>(
+            m, n, int(cnt), part, S, lds, symmetric ? 1 : 0, s0 > 0 ? 1 : 0);
+        LAUNCH_CHECK();
+    }
 }
 
 template void gram_product<float>(chf_ctx*, const float*, int64_t, const float*, int64_t, int64_t, int, int, double*,
@@ -435,19 +455,26 @@ static int cholqr_once(chf_ctx* ctx, T* X, int64_t ldx, int64_t n_rows, int m, d
     LAUNCH_CHECK();
     // X is row-major [n_rows][ldx] = column-major Xc [m][n_rows] (ld ldx).
     // X R^{-1}  <=>  Xc <- R^{-T} Xc : left-side solve with U^T.
-    if (f64) {
-        const double one = 1.0;
-        ROCBLAS_CHECK(rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                                    rocblas_diagonal_non_unit, m, rocblas_int(n_rows), &one, S, m,
-                                    reinterpret_cast<double*>(X), rocblas_int(ldx)));
-    } else {
-        float* R32 = reinterpret_cast<float*>(reinterpret_cast<char*>(S) + size_t(m) * m * sizeof(double));
+    // (in row panels: each call's block spans fewer than kBlasMaxElems elements)
+    const int64_t pt = std::max<int64_t>(1, std::min<int64_t>(n_rows, kBlasMaxElems / std::max<int64_t>(1, ldx)));
+    float* R32 = reinterpret_cast<float*>(reinterpret_cast<char*>(S) + size_t(m) * m * sizeof(double));
+    if (!f64) {
         cast_matrix_kernel<float><<<unsigned((int64_t(m) * m + 255) / 256), 256, 0, s>>>(int64_t(m) * m, S, R32);
         LAUNCH_CHECK();
-        const float one = 1.0f;
-        ROCBLAS_CHECK(rocblas_strsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                                    rocblas_diagonal_non_unit, m, rocblas_int(n_rows), &one, R32, m,
-                                    reinterpret_cast<float*>(X), rocblas_int(ldx)));
+    }
+    for (int64_t r0 = 0; r0 < n_rows; r0 += pt) {
+        const int64_t rows = std::min(pt, n_rows - r0);
+        if (f64) {
+            const double one = 1.0;
+            ROCBLAS_CHECK(rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                                        rocblas_diagonal_non_unit, m, rocblas_int(rows), &one, S, m,
+                                        reinterpret_cast<double*>(X + r0 * ldx), rocblas_int(ldx)));
+        } else {
+            const float one = 1.0f;
+            ROCBLAS_CHECK(rocblas_strsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                                        rocblas_diagonal_non_unit, m, rocblas_int(rows), &one, R32, m,
+                                        reinterpret_cast<float*>(X + r0 * ldx), rocblas_int(ldx)));
+        }
     }
     return 0;
 }
@@ -518,7 +545,8 @@ void rayleigh_ritz_t(chf_ham* H, chf_ctx* ctx, T* X, int64_t ldx, int m, double*
     // panels, in place: a panel of P rows of X (row-major, = column-major
     // Xc [m][P]) gives Qᵀ Xc, computed into the work block used as flat
     // storage of P x m values (P = n_rows ldw / m), then copied back.
-    const int64_t P = std::max<int64_t>(1, std::min<int64_t>(n_rows, n_rows * ldw / m));
+    const int64_t P = std::max<int64_t>(
+        1, std::min<int64_t>(std::min<int64_t>(n_rows, n_rows * ldw / m), kBlasMaxElems / std::max<int64_t>(ldx, m)));
     CHF_REQUIRE(P <= INT32_MAX, "rayleigh_ritz: panel beyond 32-bit BLAS");
     float* Q32 = reinterpret_cast<float*>(reinterpret_cast<char*>(Hs) + size_t(m) * m * sizeof(double));
     if (!std::is_same<T, double>::value) {
@@ -700,14 +728,14 @@ static WsNeed ws_need(const chf_ham* H, int op, chf_dtype dtype, int nvec, int64
         break;
     case CHF_WS_ORTHONORMALIZE:
         w.scratch = mm_scratch_bytes(nvec, cholqr_extra(nvec));
-        w.scratch2 = gram_slices(n_rows, nvec, nvec, es).part_bytes;
+        w.scratch2 = gram_slices(n_rows, nvec, nvec, es, nvec).part_bytes;
         break;
     case CHF_WS_RAYLEIGH_RITZ: {
         if (ldw <= 0) fail(CHF_EINVAL, "chf_workspace_bytes: Rayleigh-Ritz needs the work leading dimension");
         const int nb = int(std::min<int64_t>(nvec, ldw));
         w.kb = kb_coef_bytes(H, nb, es);
         w.scratch = mm_scratch_bytes(nvec, rr_extra(nvec));
-        w.scratch2 = gram_slices(n_rows, nvec, nb, es).part_bytes;
+        w.scratch2 = gram_slices(n_rows, nvec, nb, es, nvec).part_bytes;
         break;
     }
     case CHF_WS_LANCZOS:

@@ -368,12 +368,14 @@ __global__ void crop_kernel(int D, int S, int ox, int oy, int oz, int sym, const
 }
 
 __global__ void rows_to_box_kernel(int64_t n_rows, const int32_t* __restrict__ ijk4, const double* __restrict__ rows,
-                                   double scale, float* __restrict__ box, int D, int off) {
+                                   const double* __restrict__ base, double scale, float* __restrict__ box, int D,
+                                   int off) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n_rows || !ijk4[4 * r + 3]) return;
     const int x = ijk4[4 * r] + off, y = ijk4[4 * r + 1] + off, z = ijk4[4 * r + 2] + off;
     if (x < 0 || y < 0 || z < 0 || x >= D || y >= D || z >= D) return;
-    box[(int64_t(z) * D + y) * D + x] = float(scale * rows[r]);
+    const double v = base ? rows[r] - base[r] : rows[r];
+    box[(int64_t(z) * D + y) * D + x] = float(scale * v);
 }
 
 __global__ void box_to_rows_kernel(int64_t n_rows, const int32_t* __restrict__ ijk4, const float* __restrict__ box, int D,
@@ -827,12 +829,14 @@ int dnet_mse(dnet* N, const float* y, const float* t, int64_t n, double* loss_ho
     });
 }
 
-int chf_rows_to_box(chf_ham* H, const double* rows, double scale, float* box, int D, int off, void* stream) {
+int chf_rows_to_box(chf_ham* H, const double* rows, const double* base, double scale, float* box, int D, int off,
+                    void* stream) {
     return dguard([&] {
         if (!H || !rows || !box || D < 1) fail(CHF_EINVAL, "chf_rows_to_box: bad argument");
         hipStream_t s = static_cast<hipStream_t>(stream);
         HIP_CHECK(hipMemsetAsync(box, 0, size_t(D) * D * D * sizeof(float), s));
-        rows_to_box_kernel<<<nb(H->grid.n_rows), 256, 0, s>>>(H->grid.n_rows, H->row_ijk4.as<int32_t>(), rows, scale, box, D, off);
+        rows_to_box_kernel<<<nb(H->grid.n_rows), 256, 0, s>>>(H->grid.n_rows, H->row_ijk4.as<int32_t>(), rows, base,
+                                                              scale, box, D, off);
         LAUNCH_CHECK();
     });
 }

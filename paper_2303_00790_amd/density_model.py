@@ -50,13 +50,16 @@ def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, 
     st["scf"].fields(rho_conv)
     D, off = box_geometry(H)
     bs = torch.zeros(D ** 3, dtype=torch.float32, device="cuda")
-    bc = torch.zeros_like(bs)
+    bd = torch.zeros_like(bs)
     B.rows_to_box(H, rho_sad, SCALE, bs, D, off)
-    B.rows_to_box(H, rho_conv, SCALE, bc, D, off)
-    return Sample(bs, bc - bs, D, cluster.n_atoms, res.steps), res
+    B.rows_to_box(H, rho_conv, SCALE, bd, D, off, base=rho_sad)      # the label: rho_conv - rho_sad
+    return Sample(bs, bd, D, cluster.n_atoms, res.steps), res
 
 
-def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: float = 0.05, log=print):
+def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: float = 0.05, log=print,
+                 dtype: str = "f64"):
+    """Training data: the superposition start and the correction to the SCF
+    density converged by the FP64 path (dtype) on n seeded random clusters."""
     from synth.cluster import make_cluster
     rng = np.random.default_rng(seed0)
     data = []
@@ -66,7 +69,7 @@ def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: fl
         if c.n_atoms == 0:
             continue
         t0 = time.perf_counter()
-        smp, res = converged_sample(c, pp, log=log)
+        smp, res = converged_sample(c, pp, dtype=dtype, log=log)
         data.append(smp)
         log(f"train cluster {i}: d={d:.2f} nm Si{c.n_si}H{c.n_h} box {smp.D}^3 scf steps {res.steps} "
             f"converged {res.converged} ({time.perf_counter() - t0:.1f} s)")
@@ -124,7 +127,7 @@ def predicted_start(net, H, cluster, highpass_sigma: float = 0.0):
     return rho_sad, rho0
 
 
-def evaluate(net, clusters, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, log=print, first_iters: int = 4,
+def evaluate(net, clusters, pp, dtype: str = "f64", sre_tol_ry: float = 1e-4, log=print, first_iters: int = 4,
              highpass_sigma: float = 0.0):
     """SCF from the superposition start and from the learned start, same
     schedule and start vectors; steps to SRE < sre_tol_ry and energies."""

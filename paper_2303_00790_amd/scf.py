@@ -25,13 +25,16 @@ class ScfResult:
 
 def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nvec: int | None = None,
           x_seed: int = 2001, lanczos_seed: int = 3001, margin: float = 6.0, mix_beta: float = 0.1,
-          mix_history: int = 8, first_iters: int = 4):
+          mix_history: int = 8, first_iters: int = 4, work_cols: int = 256):
     """Hamiltonian, context, SCF state and the start block for a cluster.
 
     Anderson mixing defaults to beta = 0.1 with 8 past densities: at
     beta = 0.3 the density of clusters from 3 nm up sloshes without
     converging.  ``first_iters`` ChFSI iterations run in the first SCF step
-    (the paper's schedule: 4, then 1 per step)."""
+    (the paper's schedule: 4, then 1 per step).  The work block has
+    min(M, work_cols) columns: the filter and Rayleigh-Ritz run through it in
+    column blocks and row panels, so X is the only block of full width (at
+    5 nm in FP64, 151 GB for X against 5 GB of work)."""
     import torch
     from synth.cluster import n_states
     radius = cluster.domain_radius(margin)
@@ -57,7 +60,8 @@ def setup(cluster, pp, h: float = 0.7, dtype: str = "f64", degree: int = 10, nve
     v0[rows] = torch.from_numpy(np.random.default_rng(lanczos_seed).standard_normal(H.n_points)).cuda()
     eii = B.ion_energy(cluster.pos, cluster.species, pp)
     prm = B.ScfParams(ne, M, degree, first_iters, 1, 10, code, code, mix_history, mix_beta, 1e-12, eii)
-    return dict(H=H, ctx=ctx, prm=prm, X=X, W=torch.zeros_like(X), v0=v0, rows=rows, ne=ne, M=M)
+    W = torch.zeros((H.n_rows, min(M, work_cols)), dtype=tdt, device="cuda")
+    return dict(H=H, ctx=ctx, prm=prm, X=X, W=W, v0=v0, rows=rows, ne=ne, M=M)
 
 
 def run(state, rho0, max_steps: int = 60, sre_tol_ry: float = 1e-4, min_steps: int = 1, log=None,

@@ -187,6 +187,14 @@ def test_rows_box_round_trip(grid_system):
     ijk = s["g"].ijk + off
     assert np.allclose(b[ijk[:, 2], ijk[:, 1], ijk[:, 0]], (30.0 * vals).astype(np.float32), rtol=0, atol=0)
     assert np.count_nonzero(b) == np.count_nonzero(vals)
+    # with a base, the box holds the scaled difference taken in FP64
+    base = torch.zeros_like(rows)
+    base[s["rows"]] = torch.from_numpy(vals[::-1].copy()).cuda()
+    boxd = torch.full((D ** 3,), float("nan"), dtype=torch.float32, device="cuda")
+    B.rows_to_box(H, rows, 30.0, boxd, D, off, base=base)
+    bd = boxd.cpu().numpy().reshape(D, D, D)
+    assert np.allclose(bd[ijk[:, 2], ijk[:, 1], ijk[:, 0]], (30.0 * (vals - vals[::-1])).astype(np.float32), rtol=0,
+                       atol=0)
     back = torch.full_like(rows, float("nan"))
     B.box_to_rows(H, box, D, off, 30.0, None, back)
     got = back.cpu().numpy()
