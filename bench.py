@@ -47,6 +47,9 @@ def parse():
                     help="also run one plain 4 GiB device copy (reference dispatch for HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="JSON with counter-derived HBM bytes per H X launch for this workload")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 record (3 nm cluster, 128 FP64 vectors, degree 12: Hilbert-tiled kernel, "
+                         "neighbour-table kernel on the Hilbert and on the lexicographic order)")
     return ap.parse_args()
 
 
@@ -114,6 +117,73 @@ def host_cpu() -> str:
 
 
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix peaks
+
+
+def filter_record(B, H, X, W, degree, bounds, steps, warmup, generic, n_pts, nvec, es) -> dict:
+    """Time `steps` degree-m filter calls (after `warmup`): throughput, the H X
+    kernel's launches timed by the library, and both rooflines (the H X
+    kernel per launch; the whole pass, every kernel included)."""
+    import torch
+    a, b, a0 = bounds
+    for _ in range(warmup):
+        H.filter(X, W, degree, a, b, a0, generic=generic)
+    torch.cuda.synchronize()
+    B.timer(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        H.filter(X, W, degree, a, b, a0, generic=generic)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tm = B.timer_read()
+    B.timer(False)
+    alg = alg_bytes_per_launch(n_pts, nvec, es, degree)
+    hx_s = tm["hx_ms"] / 1e3 / max(1, tm["hx_launches"])
+    pass_gbs = alg * degree / (ms / 1e3) / 1e9
+    return {"ms_per_filter": ms, "value": n_pts * nvec / (ms / 1e3), "hx_avg_launch_ms": hx_s * 1e3,
+            "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"]),
+            "roofline": {"bound": "hbm", "achieved": alg / hx_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / hx_s / 1e9 / HBM_PEAK_GBS},
+            "pass_achieved": pass_gbs, "pass_frac": pass_gbs / HBM_PEAK_GBS}
+
+
+def fp64_record(B, steps: int, warmup: int) -> dict:
+    """The FP64 filter on the 3 nm cluster (Si705H300, 593,857 points): one
+    128-vector block, degree 12, on the blockwise Hilbert order (tiled kernel,
+    and the neighbour-table kernel on the same order) and on the
+    lexicographic order (neighbour-table kernel)."""
+    import torch
+    from synth.cluster import make_cluster
+    from synth.workloads import MODEL_PP, WORKLOADS
+    wl = WORKLOADS["d3nm"]
+    c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
+    radius = c.domain_radius()
+    out = {"workload": f"{wl.name}: {wl.description}", "vectors": wl.nvec, "degree": wl.degree, "dtype": "f64"}
+    ctx = B.Context(0)
+    for name, ordering, generic in (("hilbert_tiled", B.ORDER_HILBERT, False),
+                                    ("hilbert_neighbour_table", B.ORDER_HILBERT, True),
+                                    ("lexicographic_neighbour_table", B.ORDER_LEX, True)):
+        H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, ordering, keep_nbr=generic, dtypes=2)
+        _, rows_np, _ = H.export_ordering()
+        rows = torch.from_numpy(rows_np).cuda()
+        inside = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
+        inside[rows] = 1.0
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(wl.x_seed)
+        X = torch.randn((H.n_rows, wl.nvec), generator=gen, dtype=torch.float64, device="cuda") * inside[:, None]
+        W = torch.zeros_like(X)
+        gen.manual_seed(wl.lanczos_seed)
+        v0 = torch.randn(H.n_rows, generator=gen, dtype=torch.float64, device="cuda") * inside
+        b, tmin, _ = H.lanczos_bound(ctx, v0, 10)
+        a0 = float(H.vloc()[rows].min())
+        out["points"] = H.n_points
+        out[name] = filter_record(B, H, X, W, wl.degree, (tmin + 0.1 * (b - tmin), b, a0), steps, warmup, generic,
+                                  H.n_points, wl.nvec, 8)
+        del H, X, W
+        torch.cuda.empty_cache()
+    return out
 
 
 def gram_bench(args, B, ctx, H, wl, dtype_name, tdtype, inside):
@@ -229,6 +299,9 @@ def main():
     alg_bytes = alg_bytes_per_launch(n_pts, nvec, es, wl.degree)
     hx_avg_s = tm["hx_ms"] / 1e3 / max(1, launches)
     achieved = alg_bytes / hx_avg_s / 1e9
+    # the whole pass (H X launches, KB gathers, everything between): the
+    # algorithmic bytes of all degree steps over the measured time per pass
+    pass_gbs = alg_bytes * wl.degree / (ms / 1e3) / 1e9
     kernel = ("hx_generic_kernel" if generic else "hx_tiled_kernel")
     # HBM traffic from the committed counter runs, only if they were taken on
     # the kernel source as it is now
@@ -259,9 +332,23 @@ def main():
                      "kernel": kernel, "avg_launch_ms": hx_avg_s * 1e3,
                      "alg_bytes_per_launch": alg_bytes,
                      "kb_gather_avg_ms": tm["gather_ms"] / max(1, tm["gather_launches"]),
-                     "kb_gather_launches": tm["gather_launches"]},
+                     "kb_gather_launches": tm["gather_launches"],
+                     "pass_achieved": pass_gbs, "pass_frac": pass_gbs / HBM_PEAK_GBS},
         "wall_s": wall,
     }
+    del X, W
+    torch.cuda.empty_cache()
+    if not args.no_fp64 and args.workload == "d16nm" and not generic:
+        out["fp64_c2"] = fp64_record(B, max(3, args.steps // 2), 1)
+    learned = os.path.join(ROOT, "results", "learned_density_4nm.json")
+    if os.path.exists(learned):
+        ld = json.load(open(learned))
+        if "mean_steps_sad" in ld:
+            out["scf_iters_saved"] = {"source": "results/learned_density_4nm.json (measured separately)",
+                                      "clusters": len(ld.get("eval", [])), "dtype": ld.get("dtype"),
+                                      "mean_steps_superposition": ld["mean_steps_sad"],
+                                      "mean_steps_learned": ld["mean_steps_net"],
+                                      "max_de_per_atom_ha": ld.get("max_de_per_atom")}
     if args.copy_calibration:
         src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

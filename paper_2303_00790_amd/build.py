@@ -1,4 +1,4 @@
-"""Build libchfsi.so (HIP for gfx950) and the C oracle helpers, in-tree.
+"""Build libchfsi.so (HIP for gfx950) in-tree.
 
     python -m paper_2303_00790_amd.build        # or __graft_entry__.build()
 

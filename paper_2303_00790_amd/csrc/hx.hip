@@ -1040,10 +1040,11 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
     const __amdgpu_buffer_rsrc_t rB = make_rsrc(ent_beta + 4 * int64_t(e_blk0), unsigned(e_cnt) * 4u * es);
     const __amdgpu_buffer_rsrc_t rS = make_rsrc(ent_soff + e_blk0, unsigned(e_cnt) * 4u);
     // entries of row z: lane i holds entry i (LDS byte offset of its slot's
-    // coefficients and its 4 weights); the row's entry range comes 2 planes
-    // before the entries, which come PD planes before their use (1 for FP64,
-    // whose 4 weights take twice the registers)
+    // coefficients and its 4 weights); the row's entry range comes RL planes
+    // before the entries, which come PD planes before their use (both 1 for
+    // FP64, whose 4 weights take twice the registers)
     constexpr int PD = sizeof(T) == 4 ? 2 : 1;
+    constexpr int RL = sizeof(T) == 4 ? 2 : 1;   // lead of the entry ranges over the entries
     int2 e_rng[8];
     int e_soff[8];
     T e_b[8][4];
@@ -1065,12 +1066,15 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
         }
     };
 #pragma unroll
-    for (int z = 0; z < PD + 2; ++z) load_range(z);
+    for (int z = 0; z < PD + RL; ++z) load_range(z);
     // the X window of this column, the first two halo planes, Y_{k-1} and
     // V_eff of plane 0
+    // (X planes are loaded WL planes before the stencil first needs them: 2,
+    // or 1 for FP64 to stay within 128 registers)
+    constexpr int WL = sizeof(T) == 4 ? 2 : 1;
     V w[20];
 #pragma unroll
-    for (int i = 0; i < 14; ++i) w[i] = load_plane(i - 6);
+    for (int i = 0; i < 12 + WL; ++i) w[i] = load_plane(i - 6);
     V hv0[3], hv[3];
     load_halo(0, hv0);
     load_halo(1, hv);
@@ -1100,7 +1104,7 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
         }
         // loads, in the order they are needed: next plane's halos, Y_{k-1}
         // and V_eff first, then the entries of plane z + PD, the entry range
-        // of plane z + PD + 2 and the X plane z + 8
+        // of plane z + PD + RL and the X plane z + 8
         if (z < 6) load_halo(z + 2, hv);
         V znext = lz<V>();
         T vnext = T(0);
@@ -1109,8 +1113,8 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
             vnext = veff[base + lrow + 64 * (z + 1)];
         }
         if (z + PD < 8) load_entries(z + PD);
-        if (z + PD + 2 < 8) load_range(z + PD + 2);
-        if (z < 6) w[z + 14] = load_plane(z + 8);
+        if (z + PD + RL < 8) load_range(z + PD + RL);
+        if (z + 6 + WL < 14) w[z + 12 + WL] = load_plane(z + 6 + WL);
 
         // alpha-scaled off-diagonal stencil; the diagonal is added last
         V acc = lz<V>();

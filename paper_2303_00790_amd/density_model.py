@@ -57,13 +57,20 @@ def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, 
 
 
 def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: float = 0.05, log=print,
-                 dtype: str = "f64"):
+                 dtype: str = "f64", budget_s: float | None = None):
     """Training data: the superposition start and the correction to the SCF
-    density converged by the FP64 path (dtype) on n seeded random clusters."""
+    density converged by the FP64 path (dtype) on up to n seeded random
+    clusters; with budget_s, no new cluster is started once that many seconds
+    have passed (the data stay in device memory, so generation and training
+    share one session)."""
     from synth.cluster import make_cluster
     rng = np.random.default_rng(seed0)
     data = []
+    t_start = time.perf_counter()
     for i in range(n):
+        if budget_s is not None and time.perf_counter() - t_start > budget_s:
+            log(f"data budget of {budget_s:.0f} s reached after {len(data)} clusters")
+            break
         d = float(rng.uniform(*diam_nm))
         c = make_cluster(5.0 * d, seed0 + i, sigma_angstrom=sigma)
         if c.n_atoms == 0:

@@ -4,12 +4,15 @@ the highest occupied state; gap(d) = E0 + A / d^k; spectra at h = 0.9 bohr
 against h = 0.7 bohr).
 
     python -m paper_2303_00790_amd.gap_study --diam 1.0 1.5 2.0 2.5 3.0 --h2 0.9 --out gap.json
+    python -m paper_2303_00790_amd.gap_study --diam 5.0 --seed0 30007 --h2 0.9 --out gap5.json
+    python -m paper_2303_00790_amd.gap_study --merge gap.json gap5.json --out gap_all.json
 
-Each cluster (seed 30000 + i, position noise 0.02 angstrom) is converged by
+Each cluster (seed seed0 + i, position noise 0.02 angstrom) is converged by
 the library's SCF to SRE < 1e-4 Ry in the mixed-precision mode; the
-eigenvalues, HOMO-LUMO gap and DOS are recorded, the gap is fitted, and with
---h2 every cluster is converged again at the second spacing and the two
-spectra compared.
+eigenvalues, HOMO-LUMO gap and DOS (0.1 eV bins, HOMO at 0) are recorded, the
+gap is fitted, and with --h2 every cluster is converged again at the second
+spacing and the two spectra compared.  --merge joins the cluster lists of
+several runs (same spacing, precision and pseudopotential) and refits.
 """
 from __future__ import annotations
 
@@ -54,6 +57,8 @@ def main(argv=None):
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--degree", type=int, default=12)
     ap.add_argument("--pp", default="", help="model pseudopotential overrides, e.g. r_loc=0.9,h_s=2.0")
+    ap.add_argument("--seed0", type=int, default=30000, help="geometry seed of the first diameter")
+    ap.add_argument("--merge", nargs="+", default=None, metavar="JSON", help="join earlier runs and refit")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     pp = MODEL_PP
@@ -64,17 +69,30 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
 
+    if args.merge:
+        runs = [json.load(open(f)) for f in args.merge]
+        for key in ("h", "dtype", "pp"):
+            if any(r.get(key) != runs[0].get(key) for r in runs):
+                raise SystemExit(f"gap_study --merge: the runs differ in {key}")
+        rows = sorted((c for r in runs for c in r["clusters"]), key=lambda c: c["diam_nm"])
+        res = dict(h=runs[0]["h"], dtype=runs[0]["dtype"], pp=runs[0]["pp"], clusters=rows,
+                   merged_from=[os.path.basename(f) for f in args.merge])
+        fit_and_write(res, rows, args.out, log)
+        return res
     rows = []
     for i, d in enumerate(args.diam):
-        c = make_cluster(5.0 * d, 30000 + i, sigma_angstrom=0.02)
+        c = make_cluster(5.0 * d, args.seed0 + i, sigma_angstrom=0.02)
         r = converge(c, pp, args.h, args.dtype, args.degree, log)
-        row = dict(diam_nm=d, n_si=c.n_si, n_h=c.n_h, n_points=r["n_points"], states=r["M"], n_occ=r["n_occ"],
+        row = dict(diam_nm=d, seed=args.seed0 + i, n_si=c.n_si, n_h=c.n_h, n_points=r["n_points"], states=r["M"],
+                   n_occ=r["n_occ"],
                    steps=r["steps"], converged=r["converged"], energy=r["energy"], seconds=r["seconds"],
                    gap_ev=A.gap_ev(r["eig"], r["n_occ"]))
-        _, dens = A.dos_histogram(r["eig"], r["n_occ"])
+        centres, dens = A.dos_histogram(r["eig"], r["n_occ"])
+        row.update(dos_bin_centres_ev=[float(x) for x in centres], dos=[float(x) for x in dens])
         if args.h2:
             r2 = converge(c, pp, args.h2, args.dtype, args.degree, log)
             _, dens2 = A.dos_histogram(r2["eig"], r2["n_occ"])
+            row["dos_h2"] = [float(x) for x in dens2]
             occ = slice(0, r["n_occ"])
             e1 = (r["eig"][occ] - r["eig"][r["n_occ"] - 1]) * A.HARTREE_EV
             e2 = (r2["eig"][occ] - r2["eig"][r["n_occ"] - 1]) * A.HARTREE_EV
@@ -86,6 +104,12 @@ def main(argv=None):
         rows.append(row)
     import dataclasses
     res = dict(h=args.h, dtype=args.dtype, pp=dataclasses.asdict(pp), clusters=rows)
+    fit_and_write(res, rows, args.out, log)
+    return res
+
+
+def fit_and_write(res: dict, rows: list, out, log) -> None:
+    from . import analysis as A
     if len(rows) >= 3:
         dd, gg = [r["diam_nm"] for r in rows], [r["gap_ev"] for r in rows]
         e0, a, k, r2 = A.fit_gap(dd, gg)
@@ -94,10 +118,9 @@ def main(argv=None):
         e0, a, k, r2 = A.fit_gap(dd, gg, k=1.56)
         res["fit_k_1.56"] = dict(e0_ev=e0, a_ev=a, k=k, r2=r2)
         log(f"gap fit at the published exponent 1.56: E0 = {e0:.3f} eV, A = {a:.3f} eV, R^2 = {r2:.5f}")
-    if args.out:
-        with open(args.out, "w") as f:
+    if out:
+        with open(out, "w") as f:
             json.dump(res, f, indent=1)
-    return res
 
 
 if __name__ == "__main__":

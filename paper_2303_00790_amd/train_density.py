@@ -30,15 +30,17 @@ def main(argv=None):
     from synth.workloads import MODEL_PP
 
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--train", type=int, default=40)
-    ap.add_argument("--train-diam", type=float, nargs=2, default=(1.5, 2.5))
-    ap.add_argument("--steps", type=int, default=1500)
-    ap.add_argument("--patch", type=int, default=48)
+    ap.add_argument("--train", type=int, default=200)
+    ap.add_argument("--train-diam", type=float, nargs=2, default=(1.5, 3.0))
+    ap.add_argument("--data-budget", type=float, default=None, metavar="SECONDS",
+                    help="stop generating training clusters after this many seconds")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--patch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--channels", type=int, default=32)
     ap.add_argument("--eval", type=int, default=3)
     ap.add_argument("--eval-diam", type=float, default=3.0)
-    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--dtype", default="f64", help="SCF precision of the training labels and the evaluation")
     ap.add_argument("--eval-seed", type=int, default=20000)
     ap.add_argument("--first-iters", type=int, default=4, help="ChFSI iterations in the first SCF step of the evaluation")
     ap.add_argument("--highpass", type=float, default=0.0,
@@ -52,18 +54,20 @@ def main(argv=None):
         print(msg, flush=True)
 
     net = B.DensityNet(args.channels, seed=1)
-    res = {"channels": args.channels}
+    res = {"channels": args.channels, "dtype": args.dtype}
     if args.params_in:
         net.set_params(np.load(args.params_in).astype(np.float32))
         res["params_in"] = os.path.basename(args.params_in)
     else:
         t0 = time.perf_counter()
-        data = DM.make_dataset(args.train, 10000, tuple(args.train_diam), MODEL_PP, sigma=0.05, log=log)
+        data = DM.make_dataset(args.train, 10000, tuple(args.train_diam), MODEL_PP, sigma=0.05, log=log,
+                               dtype=args.dtype, budget_s=args.data_budget)
         t_data = time.perf_counter() - t0
         t1 = time.perf_counter()
         losses = DM.train(net, data, args.steps, patch=args.patch, lr=args.lr, log=log)
         t_train = time.perf_counter() - t1
-        res.update({"train_clusters": len(data), "train_diam_nm": list(args.train_diam), "steps": args.steps,
+        res.update({"train_clusters": len(data), "train_clusters_requested": args.train, "dtype": args.dtype,
+                    "train_diam_nm": list(args.train_diam), "steps": args.steps,
                     "patch": args.patch, "data_s": t_data, "train_s": t_train,
                     "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:]))})
         if args.params_out:
