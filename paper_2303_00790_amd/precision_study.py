@@ -6,12 +6,17 @@ block to the same SRE threshold.
     python -m paper_2303_00790_amd.precision_study --workload d3nm --out prec.json
     python -m paper_2303_00790_amd.precision_study --workload d5nm --only f64 --sre-tol 1e-5 --out f64.json
     python -m paper_2303_00790_amd.precision_study --combine f64.json f32.json --out prec.json
+    python -m paper_2303_00790_amd.precision_study --workload d5nm --only f32 --sre-tol 1e-3 --rho-out rho1.npy
+    python -m paper_2303_00790_amd.precision_study --workload d5nm --only f64 --sre-tol 1e-5 --rho-in rho1.npy
 
 Reports the converged energies, the largest eigenvalue difference over the
 occupied states, the energy difference per atom, SCF step counts and the
 time per SCF step of both runs.  --only runs one precision and writes its
 record (energy, occupied eigenvalues, steps, times); --combine compares two
 such records (so the two runs can take separate sessions on the device).
+--rho-out / --rho-in save and restart from a mixed input density, so that a
+long SCF can be split: both precisions then converge from the same density
+(and the same start vectors) to their own fixed points.
 """
 from __future__ import annotations
 
@@ -25,13 +30,21 @@ import numpy as np
 
 
 def run_one(cluster, pp, dtype: str, degree: int, log, sre_tol: float = 1e-4, max_steps: int = 80,
-            trace=None):
+            trace=None, rho_in=None, rho_out=None):
+    """One SCF from the superposition start, or from the density in rho_in
+    (.npy of the inside-point values in curve order); rho_out (optional
+    path) receives the last mixed input density in the same form."""
     import torch
     from . import scf as S
     t0 = time.perf_counter()
     st = S.setup(cluster, pp, dtype=dtype, degree=degree)
     H = st["H"]
-    rho = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
+    if rho_in:
+        rho = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
+        rho[st["rows"]] = torch.from_numpy(np.load(rho_in)).cuda()
+        log(f"{dtype}: start density from {os.path.basename(rho_in)}")
+    else:
+        rho = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"{dtype}: setup {t_setup:.1f} s, {H.n_points} points, {st['M']} states, work block {st['W'].shape[1]} columns")
@@ -40,6 +53,10 @@ def run_one(cluster, pp, dtype: str, degree: int, log, sre_tol: float = 1e-4, ma
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"{dtype}: {res.steps} SCF steps, converged {res.converged}, E = {res.energy:.10f} Ha, {dt:.1f} s")
+    if rho_out:
+        rho_last = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
+        st["scf"].fields(rho_last)
+        np.save(rho_out, rho_last[st["rows"]].cpu().numpy())
     n_occ = cluster.n_electrons // 2
     out = dict(dtype=dtype, steps=res.steps, converged=bool(res.converged), energy=res.energy,
                eig_occ=[float(x) for x in np.asarray(res.eig)[:n_occ]], seconds=dt, setup_s=t_setup,
@@ -75,6 +92,8 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=80)
     ap.add_argument("--trace", default=None, help="JSON lines, one per SCF step")
     ap.add_argument("--combine", nargs=2, metavar=("F64_JSON", "F32_JSON"), default=None)
+    ap.add_argument("--rho-in", default=None, help="start density (.npy, inside points in curve order)")
+    ap.add_argument("--rho-out", default=None, help="save the last mixed input density (.npy)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -92,8 +111,10 @@ def main(argv=None):
         info = dict(workload=wl.name, n_si=c.n_si, n_h=c.n_h, n_atoms=c.n_atoms, degree=wl.degree)
         runs = {}
         for dt in ([args.only] if args.only else ["f64", "f32"]):
-            runs[dt] = run_one(c, MODEL_PP, dt, wl.degree, log, args.sre_tol, args.max_steps, args.trace)
+            runs[dt] = run_one(c, MODEL_PP, dt, wl.degree, log, args.sre_tol, args.max_steps, args.trace,
+                               args.rho_in, args.rho_out)
             runs[dt]["cluster"] = info
+            runs[dt]["start_density"] = os.path.basename(args.rho_in) if args.rho_in else "superposition"
         res = runs[args.only] if args.only else compare(info, runs["f64"], runs["f32"])
     log(json.dumps({k: v for k, v in res.items() if k not in ("eig_occ", "step_seconds")}))
     if args.out:
