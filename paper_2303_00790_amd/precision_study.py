@@ -77,6 +77,8 @@ def compare(c_info: dict, r64: dict, r32: dict) -> dict:
                 steps_f64=r64["steps"], steps_mixed=r32["steps"], sre_tol_ry=r64["sre_tol"],
                 sre_last_f64=r64["sre_last"], sre_last_mixed=r32["sre_last"],
                 s_per_step_f64=r64["seconds"] / r64["steps"], s_per_step_mixed=r32["seconds"] / r32["steps"],
+                start_density_f64=r64.get("start_density", "superposition"),
+                start_density_mixed=r32.get("start_density", "superposition"),
                 converged=bool(r64["converged"] and r32["converged"]))
 
 

@@ -8,7 +8,8 @@ Tolerance: every output is a sum of at most a few thousand FP32 products
 support rows); the error of such a sum is bounded by a multiple of the unit
 roundoff (6e-8) times the sum of the absolute values of its terms, which the
 oracle returns beside each value; 3e-5 of that magnitude (500 roundoffs) is
-the bound used."""
+the bound used.  The whole degree-16 pass is checked by a property that
+holds at any size: p(H) is symmetric."""
 import dataclasses
 
 import numpy as np
@@ -27,7 +28,7 @@ def full_size():
     c = make_cluster(wl.radius_angstrom, wl.geometry_seed, wl.sigma)
     radius = c.domain_radius()
     print(f"case: 16 nm cluster, {wl.nvec} FP32 vectors", flush=True)
-    H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, B.ORDER_HILBERT, keep_nbr=False, dtypes=1)
+    H = B.Hamiltonian(c.pos, c.species, MODEL_PP, wl.h, radius, B.ORDER_HILBERT, keep_nbr=False, dtypes=3)
     ijk, rows, _ = H.export_ordering()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(wl.x_seed)
@@ -35,7 +36,6 @@ def full_size():
     inside = torch.zeros(H.n_rows, dtype=torch.bool, device="cuda")
     inside[torch.from_numpy(rows).cuda()] = True
     X.mul_(inside[:, None])
-    del inside
     n_r = int(np.abs(ijk).max())
     D = 2 * n_r + 1
     keys = ((ijk[:, 0].astype(np.int64) + n_r) * D + (ijk[:, 1] + n_r)) * D + (ijk[:, 2] + n_r)
@@ -60,7 +60,7 @@ def full_size():
     sample = np.concatenate([rng.choice(len(ijk), 20, replace=False), np.argsort(r2)[-4:], [int(np.argmin(r2))]])
     at_nuclei = np.round(c.pos[rng.choice(si, 4, replace=False)] / wl.h).astype(np.int64)
     pts = np.concatenate([ijk[sample].astype(np.int64), at_nuclei])
-    return dict(B=B, H=H, X=X, c=c, wl=wl, radius=radius, pp=MODEL_PP, pts=pts, rows_of=rows_of, x_at=x_at)
+    return dict(B=B, H=H, X=X, inside=inside, c=c, wl=wl, radius=radius, pp=MODEL_PP, pts=pts, rows_of=rows_of, x_at=x_at)
 
 
 def _oracle(fs):
@@ -97,3 +97,38 @@ def test_filter_first_step_full_size(full_size):
     ref = (s1 / e) * (hx - cc * x)
     bound = abs(s1 / e) * (mag + abs(cc) * np.abs(x))
     assert np.all(np.abs(got - ref) <= 3e-5 * bound)
+
+
+def test_full_pass_is_a_symmetric_operator(full_size):
+    # The whole degree-16 pass as the benchmark runs it (bounds as the
+    # benchmark takes them) applies p(H) with H symmetric (zero padding
+    # outside the sphere, KB term B h B^T), so G = X^T p(H) X must be
+    # symmetric at any size.  A wrong neighbour, halo plane or tile edge, or
+    # a KB scatter that does not mirror its gather, breaks the symmetry at
+    # O(1) in the entries it touches; FP32 rounding over 16 steps leaves a
+    # relative asymmetry of order 1e-6.
+    fs = full_size
+    B, H, X, wl = fs["B"], fs["H"], fs["X"], fs["wl"]
+    ctx = B.Context(0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl.lanczos_seed)
+    inside = fs["inside"]
+    v0 = torch.randn(H.n_rows, generator=gen, dtype=torch.float64, device="cuda") * inside
+    b, tmin, _ = H.lanczos_bound(ctx, v0, 10)
+    del v0
+    vloc = H.vloc()
+    a0 = float(vloc[inside].min())
+    del vloc
+    a = tmin + 0.1 * (b - tmin)
+    Xf = X.clone()
+    W = torch.empty_like(Xf)
+    H.filter(Xf, W, wl.degree, a, b, a0)
+    del W
+    assert bool(torch.isfinite(Xf).all())
+    G = torch.empty((wl.nvec, wl.nvec), dtype=torch.float64, device="cuda")
+    B.gram(ctx, X, Xf, G)
+    del Xf
+    G = G.cpu().numpy()
+    asym = np.abs(G - G.T).max() / np.abs(G).max()
+    print(f"max |G - G^T| / max |G| = {asym:.3e}")
+    assert asym < 1e-4, asym
