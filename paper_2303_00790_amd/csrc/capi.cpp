@@ -239,7 +239,6 @@ int ham_build(const chf_grid_desc* gd, const chf_atoms* atoms, const chf_pp* pp,
             upload(H->ent_atom, ea, s);
         }
         if (gd->ordering == CHF_ORDER_HILBERT) {
-            upload(H->ent_slot, H->proj.ent_slot, s);
             // staged tile kernel: LDS offset of each entry's slot, and per block,
             // wave quad (4 consecutive rows) and plane the quad's largest count
             std::vector<int32_t> soff(H->proj.ent_slot.size());

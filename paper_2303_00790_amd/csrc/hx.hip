@@ -446,41 +446,34 @@ __device__ inline void bstore(V v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
-// Workgroup of 64 columns x LANES lanes; a lane holds 8 bytes (2 floats or
-// 1 double) of an 8*LANES-byte vector chunk; one workgroup per tile (one 8^3
-// block x one vector chunk).  LANES = 16 (used) gives 128-byte row segments
-// and 1024 threads; LANES = 8 gives 64-byte segments and half the LDS, so two
-// workgroups share a CU, but measured 18 % slower on the 16 nm cluster (half
-// cache lines per request).  The KB coefficients of the atoms touching the
-// block can be staged in LDS (STAGE, up to kMaxBlockAtoms) instead of read
-// from global memory.
+// Unstaged tile kernel: one workgroup per tile (one 8^3 block x one 128-byte
+// vector chunk), 1024 threads = 64 columns x 16 lanes; a lane holds 8 bytes
+// (2 floats or 1 double) of the chunk.  It serves the blocks the staged tile
+// kernel below cannot take (more than kMaxBlockAtoms projector atoms touch
+// the block), the Laplacian-only products of the Poisson solver and
+// Hamiltonians without projectors: the stencil is applied in a z-march, the
+// eight output rows wait in registers, and the KB term is added after the
+// march from the coefficients in global memory.
 constexpr int kMaxBlockAtoms = 64;
+constexpr int kLanes = 16;
 
-template <class T, bool STAGE, int LANES>
-__global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
-                                                        const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
-                                                        const int32_t* __restrict__ ent_off,
-                                                        const int32_t* __restrict__ ent_atom,
-                                                        const uint8_t* __restrict__ ent_slot,
-                                                        const T* __restrict__ ent_beta,
-                                                        const int32_t* __restrict__ blk_atom_off,
-                                                        const int32_t* __restrict__ blk_atoms, const T* __restrict__ C,
-                                                        int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
-                                                        int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
+template <class T>
+__global__ void __launch_bounds__(64 * kLanes) hx_tiled_kernel(int64_t n_blocks, int n_chunks, const int32_t* __restrict__ bnb,
+                                                         const uint64_t* __restrict__ bmask, const T* __restrict__ veff,
+                                                         const int32_t* __restrict__ ent_off,
+                                                         const int32_t* __restrict__ ent_atom,
+                                                         const T* __restrict__ ent_beta, const T* __restrict__ C,
+                                                         int nvec, const T* __restrict__ X, int64_t ldx, T* Y,
+                                                         int64_t ldy, const T* Z, int64_t ldz, StepCoef<T> k) {
     using V = typename Lane<T>::V;
+    constexpr int LANES = kLanes;
     constexpr int LN = Lane<T>::N;       // elements per lane
     constexpr int CH = LANES * LN;       // vectors per chunk
-    constexpr int NT = 64 * LANES;       // threads
-    constexpr int LSH = LANES == 16 ? 4 : 3;
+    constexpr int LSH = 4;
     constexpr int CPW = 64 / LANES;      // columns per wave
-    static_assert(LANES == 16 || LANES == 8, "LANES is 8 or 16");
     // LDS plane: the full 20 x 20 square x in [-6, 14), y in [-6, 14) (corners
     // unused) so every neighbour is a constant offset from the centre
     __shared__ V plane[2][400][LANES];
-    // staged KB coefficients [atom slot][channel pair][lane][2]: a lane's two
-    // channels of a pair are adjacent, so one 16-byte read per pair with a
-    // 16-byte lane stride (conflict-free across the 16 lanes of a column)
-    __shared__ V cst[STAGE ? kMaxBlockAtoms : 1][2][LANES][2];
 
     // XCD-aware tile order: workgroup ids are dealt round-robin to the 8
     // XCDs; give each XCD a contiguous run of the tile sequence (blocks in
@@ -508,33 +501,25 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
         return make_rsrc(nb >= 0 ? X + int64_t(nb) * kBlockPts * ldx : X, nb >= 0 ? blk_bytes : 0u);
     };
 
-    struct TileIO {
-        int64_t blk;
-        int chunk;
-        bool vok;
-        unsigned off_x, off_z;
-        int32_t nbs[6];
-        __amdgpu_buffer_rsrc_t rOwn, rZm, rZp, rH[3], rZ;
-        unsigned hoff[3];
-    };
-    TileIO io;
-    io.blk = tile / n_chunks;
-    io.chunk = int(tile - io.blk * n_chunks);
+    const int64_t blk = tile / n_chunks;
+    const int chunk = int(tile - blk * n_chunks);
+    int32_t nbs[6];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) io.nbs[f] = bnb[6 * io.blk + f];
-    {
-        const int vbase = io.chunk * CH + p * LN;
-        io.vok = vbase < nvec;
-        io.off_x = io.vok ? (unsigned(cx + 8 * cy) * unsigned(ldx) + unsigned(vbase)) * es : kOOB;
-        io.off_z = io.vok ? (unsigned(cx + 8 * cy) * unsigned(ldz) + unsigned(vbase)) * es : kOOB;
-    }
-    io.rOwn = res_x(int32_t(io.blk));
-    io.rZm = res_x(io.nbs[4]);
-    io.rZp = res_x(io.nbs[5]);
-    io.rZ = make_rsrc(Z ? Z + io.blk * kBlockPts * ldz : X, Z ? unsigned(kBlockPts) * unsigned(ldz) * es : 0u);
+    for (int f = 0; f < 6; ++f) nbs[f] = bnb[6 * blk + f];
+    const int vbase = chunk * CH + p * LN;
+    const bool vok = vbase < nvec;
+    const unsigned off_x = vok ? (unsigned(cx + 8 * cy) * unsigned(ldx) + unsigned(vbase)) * es : kOOB;
+    const unsigned off_z = vok ? (unsigned(cx + 8 * cy) * unsigned(ldz) + unsigned(vbase)) * es : kOOB;
+    const __amdgpu_buffer_rsrc_t rOwn = res_x(int32_t(blk));
+    const __amdgpu_buffer_rsrc_t rZm = res_x(nbs[4]);
+    const __amdgpu_buffer_rsrc_t rZp = res_x(nbs[5]);
+    const __amdgpu_buffer_rsrc_t rZ =
+        make_rsrc(Z ? Z + blk * kBlockPts * ldz : X, Z ? unsigned(kBlockPts) * unsigned(ldz) * es : 0u);
     // Halo slot u of a wave covers CPW consecutive halo rows, all on one side
     // of the block (48 rows per side), so the side is wave-uniform.
     int hrow[3];
+    __amdgpu_buffer_rsrc_t rH[3];
+    unsigned hoff[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
         const int hr0 = CPW * wave + 64 * u;
@@ -548,252 +533,119 @@ __global__ void __launch_bounds__(64 * LANES) hx_tiled_kernel(int64_t n_blocks, 
             lx = side == 0 ? 2 + c6 : c6;
             x = side == 0 ? c6 - 6 : 8 + c6;
             y = ly;
-            nb = side == 0 ? io.nbs[0] : io.nbs[1];
+            nb = side == 0 ? nbs[0] : nbs[1];
         } else {
             const int r6 = rem / 8;
             lx = rem % 8;
             ly = side == 2 ? 2 + r6 : r6;
             x = lx;
             y = side == 2 ? r6 - 6 : 8 + r6;
-            nb = side == 2 ? io.nbs[2] : io.nbs[3];
+            nb = side == 2 ? nbs[2] : nbs[3];
         }
         hrow[u] = (y + 6) * 20 + (x + 6);
-        io.rH[u] = res_x(__builtin_amdgcn_readfirstlane(nb));
-        io.hoff[u] = io.vok ? (unsigned(lx + 8 * ly) * unsigned(ldx) + unsigned(io.chunk * CH + p * LN)) * es : kOOB;
+        rH[u] = res_x(__builtin_amdgcn_readfirstlane(nb));
+        hoff[u] = vok ? (unsigned(lx + 8 * ly) * unsigned(ldx) + unsigned(vbase)) * es : kOOB;
     }
-    auto load_plane = [&](const TileIO& io, int zz) -> V {
-        if (zz < 0) return bload<V>(io.rZm, io.off_x + unsigned(zz + 8) * plane_x);
-        if (zz >= 8) return bload<V>(io.rZp, io.off_x + unsigned(zz - 8) * plane_x);
-        return bload<V>(io.rOwn, io.off_x + unsigned(zz) * plane_x);
+    auto load_plane = [&](int zz) -> V {
+        if (zz < 0) return bload<V>(rZm, off_x + unsigned(zz + 8) * plane_x);
+        if (zz >= 8) return bload<V>(rZp, off_x + unsigned(zz - 8) * plane_x);
+        return bload<V>(rOwn, off_x + unsigned(zz) * plane_x);
     };
-    auto load_halo = [&](const TileIO& io, int z, V* hv) {
+    auto load_halo = [&](int z, V* hv) {
 #pragma unroll
-        for (int u = 0; u < 3; ++u) hv[u] = bload<V>(io.rH[u], io.hoff[u] + unsigned(z) * plane_x);
+        for (int u = 0; u < 3; ++u) hv[u] = bload<V>(rH[u], hoff[u] + unsigned(z) * plane_x);
     };
     auto store_halo = [&](int b, const V* hv) {
 #pragma unroll
         for (int u = 0; u < 3; ++u) plane[b][hrow[u]][p] = hv[u];
     };
-    auto load_z = [&](const TileIO& io, int z) -> V {
-        return bload<V>(io.rZ, io.off_z + unsigned(z) * plane_z);
-    };
+    auto load_z = [&](int z) -> V { return bload<V>(rZ, off_z + unsigned(z) * plane_z); };
 
-    {
-        const int vbase = io.chunk * CH + p * LN;
-        const int64_t base = io.blk * kBlockPts;
-        const int64_t cur_blk = io.blk;
-        const bool cur_vok = io.vok;
-        const int lrow = cx + 8 * cy;             // this column's row in plane 0
-        // STAGE: the KB term is applied inside the march, row z at plane z.
-        // The entries of row z (atom slot, h_l beta_lm) are loaded by the
-        // column's 16 lanes together (lane i holds entry i) PD planes ahead,
-        // their row offsets PD + 1 planes ahead, and broadcast across the
-        // 16-lane group (one DPP row) when used.  The block atoms'
-        // coefficients are staged in LDS before the march.
-        constexpr bool INMARCH = STAGE && LANES == 16;
-        constexpr int PD = sizeof(T) == 4 ? 2 : 1;
-        constexpr bool KEEP_R = !INMARCH;
-        const bool kb = ent_off != nullptr;
-        int na = 0, a0 = 0;
-        V cstage[4];
-        if (STAGE && kb) {
-            a0 = blk_atom_off[cur_blk];
-            na = min(blk_atom_off[cur_blk + 1] - a0, kMaxBlockAtoms);
+    const int64_t base = blk * kBlockPts;
+    const int lrow = cx + 8 * cy;             // this column's row in plane 0
+    // the X window of this column, the first two halo planes and Y_{k-1} of
+    // plane 0
+    V w[20];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = t + NT * u;         // (atom slot, lm, lane)
-                const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
-                const int vb = io.chunk * CH + lp * LN;
-                if (sl < na && vb < nvec)         // staged with alpha applied
-                    cstage[u] = lscale(k.alpha, *reinterpret_cast<const V*>(C + (int64_t(blk_atoms[a0 + sl]) * 4 + lm) * nvec + vb));
-                else
-                    cstage[u] = lz<V>();
-            }
+    for (int i = 0; i < 14; ++i) w[i] = load_plane(i - 6);
+    V hv0[3], hv[3];
+    load_halo(0, hv0);
+    load_halo(1, hv);
+    V zcur = load_z(0);
+    store_halo(0, hv0);
+    plane[0][ctr][p] = w[6];
+    __syncthreads();
+
+    const __amdgpu_buffer_rsrc_t rY = make_rsrc(Y + base * ldy, unsigned(kBlockPts) * unsigned(ldy) * es);
+    const unsigned off_y = vok ? (unsigned(lrow) * unsigned(ldy) + unsigned(vbase)) * es : kOOB;
+    V r[8];
+    const T* vr = veff ? veff + base : nullptr;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const int b = z & 1;
+        // stage plane z + 1 (its loads were issued one plane ago), then
+        // issue the loads for planes further ahead
+        if (z < 7) {
+            store_halo(b ^ 1, hv);
+            plane[b ^ 1][ctr][p] = w[z + 7];
         }
-        // the X window of this column, the first two halo planes and Y_{k-1}
-        // of plane 0 (issued after the coefficient loads, whose chain of
-        // dependent loads is the longest)
-        V w[20];
+        if (z < 6) load_halo(z + 2, hv);
+        V znext = lz<V>();
+        if (z < 7) znext = load_z(z + 1);
+        if (z < 6) w[z + 14] = load_plane(z + 8);
+
+        // unscaled stencil (c_0 x + sum_s c_s (six neighbours at distance s))
+        V acc = lscale(k.c[0], w[z + 6]);
 #pragma unroll
-        for (int i = 0; i < 14; ++i) w[i] = load_plane(io, i - 6);
-        V hv0[3], hv[3];
-        load_halo(io, 0, hv0);
-        load_halo(io, 1, hv);
-        V zcur = load_z(io, 0);
-        int e_lo[8], e_hi[8], e_slot[8];
-        T e_b[8][4];
-        auto load_offsets = [&](int z) {
-            e_lo[z] = ent_off[base + lrow + 64 * z];
-            e_hi[z] = ent_off[base + lrow + 64 * z + 1];
-        };
-        auto load_entries = [&](int z) {
-            const int en = e_lo[z] + p;
-            e_slot[z] = 0;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) e_b[z][m] = T(0);
-            if (en < e_hi[z] && p < 16) {
-                e_slot[z] = ent_slot[en];
-                load4(ent_beta + 4 * int64_t(en), e_b[z]);
-            }
-        };
-        if (INMARCH && kb) {
-#pragma unroll
-            for (int z = 0; z <= PD; ++z) load_offsets(z);
+        for (int s = 1; s <= 6; ++s) {
+            V sum = ladd(w[z + 6 - s], w[z + 6 + s]);
+            sum = ladd(sum, plane[b][ctr - s][p]);
+            sum = ladd(sum, plane[b][ctr + s][p]);
+            sum = ladd(sum, plane[b][ctr - 20 * s][p]);
+            sum = ladd(sum, plane[b][ctr + 20 * s][p]);
+            acc = lfma(k.c[s], sum, acc);
         }
-        store_halo(0, hv0);
-        plane[0][ctr][p] = w[6];
-        if (STAGE && kb) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = t + NT * u;
-                const int sl = e >> (LSH + 2), lm = (e >> LSH) & 3, lp = e & (LANES - 1);
-                if (sl < kMaxBlockAtoms) cst[sl][lm >> 1][lp][lm & 1] = cstage[u];
-            }
-        }
+        const V xc = w[z + 6];
+        if (vr) acc = lfma(vr[lrow + 64 * z], xc, acc);
+        V y = lscale(k.alpha, lfma(-k.shift, xc, acc));
+        if (Z) y = lfma(-k.beta, zcur, y);
+        r[z] = y;
+        zcur = znext;
         __syncthreads();
-        if (INMARCH && kb) {
-#pragma unroll
-            for (int z = 0; z < PD; ++z) load_entries(z);
-        }
+    }
 
-        const __amdgpu_buffer_rsrc_t rY = make_rsrc(Y + base * ldy, unsigned(kBlockPts) * unsigned(ldy) * es);
-        const unsigned off_y = cur_vok ? (unsigned(lrow) * unsigned(ldy) + unsigned(vbase)) * es : kOOB;
-        V r[8];
-        const T* vr = veff ? veff + base : nullptr;
+    // KB scatter after the march, in rounds so that the entry loads of all
+    // eight rows are in flight together
+    if (ent_off && vok) {
+        int e0[8], e1[8];
+        int nmax = 0;
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
-            const int b = z & 1;
-            // stage plane z + 1 (its loads were issued one plane ago), then
-            // issue the loads for planes further ahead
-            if (z < 7) {
-                store_halo(b ^ 1, hv);
-                plane[b ^ 1][ctr][p] = w[z + 7];
-            }
-            if (z < 6) load_halo(io, z + 2, hv);
-            V znext = lz<V>();
-            if (z < 7) znext = load_z(io, z + 1);
-            if (z < 6) w[z + 14] = load_plane(io, z + 8);
-            if (INMARCH && kb) {
-                if (z + PD + 1 < 8) load_offsets(z + PD + 1);
-                if (z + PD < 8) load_entries(z + PD);
-            }
-
-            const int l = lrow + 64 * z;
-            // alpha-scaled off-diagonal stencil first; the diagonal, which
-            // needs V_eff(p) from memory, is added last
-            // (the unstaged variant keeps the unscaled form, which needs
-            // fewer registers there: its eight output rows wait in registers
-            // for the KB scatter after the march)
-            V acc = INMARCH ? lz<V>() : lscale(k.c[0], w[z + 6]);
-#pragma unroll
-            for (int s = 1; s <= 6; ++s) {
-                V sum = ladd(w[z + 6 - s], w[z + 6 + s]);
-                sum = ladd(sum, plane[b][ctr - s][p]);
-                sum = ladd(sum, plane[b][ctr + s][p]);
-                sum = ladd(sum, plane[b][ctr - 20 * s][p]);
-                sum = ladd(sum, plane[b][ctr + 20 * s][p]);
-                if constexpr (INMARCH)
-                    acc = s == 1 ? lscale(k.ac[1], sum) : lfma(k.ac[s], sum, acc);
-                else
-                    acc = lfma(k.c[s], sum, acc);
-            }
-            const V xc = w[z + 6];
-            if (INMARCH && kb) {
-                // KB term of row z: sum over its entries of h_l beta_lm C_lm
-                // (slot offsets added to a per-lane base: the array's LDS
-                // address is beyond the 16-bit offset field)
-                const V* cst_lane = &cst[0][0][p][0];
-                const int cnt = e_hi[z] - e_lo[z];
-                static_for<0, 16>([&](auto kc) {
-                    constexpr int kk = decltype(kc)::value;
-                    if (kk < cnt) {
-                        const int sl = row_bcast<kk>(e_slot[z]);
-                        const V* c01 = cst_lane + sl * (4 * LANES);
-                        const V* c23 = c01 + 2 * LANES;
-                        acc = lfma(row_bcast<kk>(e_b[z][0]), c01[0], acc);
-                        acc = lfma(row_bcast<kk>(e_b[z][1]), c01[1], acc);
-                        acc = lfma(row_bcast<kk>(e_b[z][2]), c23[0], acc);
-                        acc = lfma(row_bcast<kk>(e_b[z][3]), c23[1], acc);
-                    }
-                });
-                for (int en = e_lo[z] + 16; en < e_hi[z]; ++en) {     // rows with more than 16 entries
-                    const T* bb = ent_beta + 4 * int64_t(en);
-                    const int sl = ent_slot[en];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) acc = lfma(bb[m], cst[sl][m >> 1][p][m & 1], acc);
-                }
-            }
-            V y;
-            if constexpr (INMARCH) {
-                const T dg = vr ? T(fma(k.alpha, vr[l], k.d0)) : k.d0;
-                y = lfma(dg, xc, acc);
-            } else {
-                if (vr) acc = lfma(vr[l], xc, acc);
-                y = lscale(k.alpha, lfma(-k.shift, xc, acc));
-            }
-            if (Z) y = lfma(-k.beta, zcur, y);
-            if (KEEP_R) {
-                r[z] = y;
-            } else {
-                const bool in = (bmask[8 * cur_blk + z] >> lrow) & 1;
-                bstore<V>(in ? y : lz<V>(), rY, off_y + unsigned(z) * plane_y);
-            }
-            zcur = znext;
-            __syncthreads();
+            const int64_t row = base + lrow + 64 * z;
+            e0[z] = ent_off[row];
+            e1[z] = ent_off[row + 1];
+            nmax = max(nmax, e1[z] - e0[z]);
         }
-
-        if (!INMARCH) {
-            // KB scatter after the march (block atom lists too long to stage,
-            // or 8-lane tiles), in rounds so that the entry loads of all rows
-            // are in flight together
-            if (kb && cur_vok) {
-                int e0[8], e1[8];
-                int nmax = 0;
-#pragma unroll
-                for (int z = 0; z < 8; ++z) {
-                    const int64_t row = base + lrow + 64 * z;
-                    e0[z] = ent_off[row];
-                    e1[z] = ent_off[row + 1];
-                    nmax = max(nmax, e1[z] - e0[z]);
-                }
-                for (int j = 0; j < nmax; ++j) {
-#pragma unroll
-                    for (int z = 0; z < 8; ++z) {
-                        const int en = e0[z] + j;
-                        if (en < e1[z]) {
-                            const T* bb = ent_beta + 4 * int64_t(en);
-                            V c0, c1, c2, c3;
-                            if (STAGE) {
-                                const int sl = ent_slot[en];
-                                c0 = cst[sl][0][p][0];
-                                c1 = cst[sl][0][p][1];
-                                c2 = cst[sl][1][p][0];
-                                c3 = cst[sl][1][p][1];
-                            } else {
-                                const T* ca = C + int64_t(ent_atom[en]) * 4 * int64_t(nvec) + vbase;
-                                c0 = *reinterpret_cast<const V*>(ca);
-                                c1 = *reinterpret_cast<const V*>(ca + nvec);
-                                c2 = *reinterpret_cast<const V*>(ca + 2 * nvec);
-                                c3 = *reinterpret_cast<const V*>(ca + 3 * nvec);
-                            }
-                            V acc = lscale(bb[0], c0);
-                            acc = lfma(bb[1], c1, acc);
-                            acc = lfma(bb[2], c2, acc);
-                            acc = lfma(bb[3], c3, acc);
-                            r[z] = lfma(k.alpha, acc, r[z]);
-                        }
-                    }
-                }
-            }
-        }
-        if (KEEP_R) {
+        for (int j = 0; j < nmax; ++j) {
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
-                const bool in = (bmask[8 * cur_blk + z] >> lrow) & 1;
-                bstore<V>(in ? r[z] : lz<V>(), rY, off_y + unsigned(z) * plane_y);
+                const int en = e0[z] + j;
+                if (en < e1[z]) {
+                    const T* bb = ent_beta + 4 * int64_t(en);
+                    const T* ca = C + int64_t(ent_atom[en]) * 4 * int64_t(nvec) + vbase;
+                    V acc = lscale(bb[0], *reinterpret_cast<const V*>(ca));
+                    acc = lfma(bb[1], *reinterpret_cast<const V*>(ca + nvec), acc);
+                    acc = lfma(bb[2], *reinterpret_cast<const V*>(ca + 2 * nvec), acc);
+                    acc = lfma(bb[3], *reinterpret_cast<const V*>(ca + 3 * nvec), acc);
+                    r[z] = lfma(k.alpha, acc, r[z]);
+                }
             }
         }
-
+    }
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool in = (bmask[8 * blk + z] >> lrow) & 1;
+        bstore<V>(in ? r[z] : lz<V>(), rY, off_y + unsigned(z) * plane_y);
     }
 }
 
@@ -1207,43 +1059,29 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
     }
 }
 
-constexpr int kLanes = 16;
-
-template <class T, int LANES>
-static void launch_hx_tiled_l(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz,
-                              int nvec, const T* C, double alpha, double shift, double beta, hipStream_t s,
-                              bool lap_only) {
-    constexpr int CH = LANES * Lane<T>::N;
+template <class T>
+void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
+                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only) {
+    constexpr int CH = kLanes * Lane<T>::N;
     const int n_chunks = (nvec + CH - 1) / CH;
     const int64_t nt = H->grid.n_blocks * int64_t(n_chunks);
-    const dim3 grid(unsigned(((nt + 7) / 8) * 8)), block(64 * LANES);
+    const dim3 grid(unsigned(((nt + 7) / 8) * 8)), block(64 * kLanes);
     const bool kb = !lap_only && H->proj.n_proj > 0;
     const bool stage = kb && H->proj.max_block_atoms <= kMaxBlockAtoms;
     const int32_t* eo = kb ? H->ent_off32.as<int32_t>() : nullptr;
     const StepCoef<T> coef = make_coef<T>(H, alpha, shift, beta);
     const T* veff = lap_only ? nullptr : veff_of<T>(H);
-#define CHF_TILED_ARGS                                                                                              \
-    H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(), H->block_mask.as<uint64_t>(), veff, eo,                \
-        H->ent_atom.as<int32_t>(), H->ent_slot.as<uint8_t>(), ent_beta_of<T>(H), H->blk_atom_off.as<int32_t>(),     \
-        H->blk_atoms.as<int32_t>(), C, nvec, X, ldx, Y, ldy, Z, ldz, coef
-    if (stage && LANES == 16)
+    if (stage)
         hx_tile_kernel<T><<<grid, block, 0, s>>>(H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(),
                                                 H->block_mask.as<uint64_t>(), veff, eo, H->ent_soff.as<int32_t>(),
                                                 ent_beta_of<T>(H), H->quad_count.as<uint64_t>(),
                                                 H->blk_atom_off.as<int32_t>(), H->blk_atoms.as<int32_t>(), C, nvec, X,
                                                 ldx, Y, ldy, Z, ldz, coef);
-    else if (stage)
-        hx_tiled_kernel<T, true, LANES><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
     else
-        hx_tiled_kernel<T, false, LANES><<<grid, block, 0, s>>>(CHF_TILED_ARGS);
-#undef CHF_TILED_ARGS
+        hx_tiled_kernel<T><<<grid, block, 0, s>>>(H->grid.n_blocks, n_chunks, H->block_nbr.as<int32_t>(),
+                                                 H->block_mask.as<uint64_t>(), veff, eo, H->ent_atom.as<int32_t>(),
+                                                 ent_beta_of<T>(H), C, nvec, X, ldx, Y, ldy, Z, ldz, coef);
     LAUNCH_CHECK();
-}
-
-template <class T>
-void launch_hx_tiled(chf_ham* H, const T* X, int64_t ldx, T* Y, int64_t ldy, const T* Z, int64_t ldz, int nvec,
-                     const T* C, double alpha, double shift, double beta, hipStream_t s, bool lap_only) {
-    launch_hx_tiled_l<T, kLanes>(H, X, ldx, Y, ldy, Z, ldz, nvec, C, alpha, shift, beta, s, lap_only);
 }
 
 // ---------------------------------------------------------------------------

@@ -174,7 +174,6 @@ struct chf_ham {
     chf::DevBuf ent_off;        // int64 [n_rows + 1]
     chf::DevBuf ent_off32;      // int32 [n_rows + 1] (pairs < 2^31)
     chf::DevBuf ent_atom;       // int32 [pairs]
-    chf::DevBuf ent_slot;       // uint8 [pairs] slot of the entry's atom in its block list
     chf::DevBuf ent_soff;       // int32 [pairs] LDS byte offset of that slot's staged coefficients (slot * 512)
     chf::DevBuf quad_count;     // uint64 [n_blocks][16]: byte z = largest entry count of the wave's
                                 //   4 rows (quad) in plane z, capped at 255
