@@ -48,7 +48,18 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--params-out", default=None)
     ap.add_argument("--params-in", default=None, help="skip data and training; evaluate these weights")
+    ap.add_argument("--merge", nargs="+", default=None, metavar="JSON",
+                    help="combine a training record and evaluation records (same weights, same diameter) into --out")
+    ap.add_argument("--test-record", default=None, metavar="JSON",
+                    help="with --merge: an evaluation record of one small cluster, kept as the test case")
     args = ap.parse_args(argv)
+    if args.merge:
+        res = merge_records(args.merge, args.test_record)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(res, f, indent=1)
+        print(json.dumps({k: v for k, v in res.items() if k != "eval"}))
+        return
 
     def log(msg):
         print(msg, flush=True)
@@ -86,6 +97,40 @@ def main(argv=None):
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)
+
+
+def merge_records(paths, test_path=None) -> dict:
+    """One record from a training run and evaluation runs of its weights:
+    the training fields, the evaluation rows of all runs in order, their
+    means, and (test_path) one small cluster's evaluation as the test case."""
+    recs = [json.load(open(p)) for p in paths]
+    train = next((r for r in recs if "train_clusters" in r), None)
+    evals = [r for r in recs if r.get("eval")]
+    diams = {r["eval_diam_nm"] for r in evals}
+    sigmas = {r["highpass_sigma"] for r in evals}
+    dtypes = {r["dtype"] for r in evals}
+    if len(diams) > 1 or len(sigmas) > 1 or len(dtypes) > 1:
+        raise SystemExit("merge: evaluation records differ in diameter, high-pass width or dtype")
+    rows = [row for r in evals for row in r["eval"]]
+    res = {"channels": (train or evals[0])["channels"], "dtype": dtypes.pop() if dtypes else None,
+           "train": {k: v for k, v in (train or {}).items() if k not in ("eval",)},
+           "eval_diam_nm": diams.pop() if diams else None,
+           "eval_seeds": [s for r in evals for s in r["eval_seeds"]],
+           "first_iters": evals[0]["first_iters"] if evals else None,
+           "highpass_sigma": sigmas.pop() if sigmas else None,
+           "eval": rows}
+    if rows:
+        res.update({"mean_steps_sad": float(np.mean([r["steps_sad"] for r in rows])),
+                    "mean_steps_net": float(np.mean([r["steps_net"] for r in rows])),
+                    "max_de_per_atom": float(max(r["de_per_atom"] for r in rows))})
+    if test_path:
+        t = json.load(open(test_path))
+        row = t["eval"][0]
+        res["test_cluster"] = {"diam_nm": t["eval_diam_nm"], "seed": t["eval_seeds"][0],
+                               "highpass_sigma": t["highpass_sigma"], "dtype": t["dtype"],
+                               "steps_sad": row["steps_sad"], "steps_net": row["steps_net"],
+                               "de_per_atom": row["de_per_atom"]}
+    return res
 
 
 if __name__ == "__main__":
