@@ -164,11 +164,13 @@ static rocblas_status gemm_sb(rocblas_handle h, rocblas_int M, rocblas_int N, ro
 // Gram S = A^T B over n_rows rows.  X^T X is a plain GEMM, so the products of
 // row slices run as strided-batched rocBLAS GEMMs (MFMA, accumulating in the
 // block precision within a slice) into partials that are summed in FP64.
-// Slices: at least kGramMinSliceRows rows, at most kGramMaxSlices per batch,
-// and every GEMM operand spans fewer than kBlasMaxElems elements (the BLAS
-// calls take 32-bit sizes and offsets); the slices run in groups whose
-// partials fit kGramPartBytes, each group's sum added to S in slice order.
-constexpr int64_t kGramMinSliceRows = 4096;
+// Slices hold at most kGramSliceRows rows whatever the width, so an FP32
+// sum never runs over more rows than that (the slice count grows with the
+// grid instead); every GEMM operand spans fewer than kBlasMaxElems elements
+// (the BLAS calls take 32-bit sizes and offsets); the slices run in groups
+// of at most kGramMaxSlices whose partials fit kGramPartBytes, each group's
+// sum added to S in slice order.
+constexpr int64_t kGramSliceRows = 8192;
 constexpr int64_t kGramMaxSlices = 256;
 constexpr size_t kGramPartBytes = size_t(1) << 30;
 constexpr int64_t kBlasMaxElems = (int64_t(1) << 31) - (int64_t(1) << 20);
@@ -183,11 +185,11 @@ struct GramSlices {
 
 static GramSlices gram_slices(int64_t n_rows, int m, int n, size_t elem_bytes, int64_t ld) {
     const size_t per = size_t(m) * size_t(n) * elem_bytes;
-    int64_t ns = std::min<int64_t>(kGramMaxSlices, std::max<int64_t>(1, n_rows / kGramMinSliceRows));
-    const int64_t max_group = std::max<int64_t>(1, int64_t(kGramPartBytes / std::max<size_t>(1, per)));
-    ns = std::max<int64_t>(1, std::min<int64_t>(ns, max_group));
+    const int64_t ns = std::max<int64_t>(1, (n_rows + kGramSliceRows - 1) / kGramSliceRows);
+    const int64_t max_group =
+        std::max<int64_t>(1, std::min<int64_t>(kGramMaxSlices, int64_t(kGramPartBytes / std::max<size_t>(1, per))));
     GramSlices g;
-    g.rows = std::max<int64_t>(1, (n_rows + ns - 1) / ns);
+    g.rows = std::max<int64_t>(1, (n_rows + ns - 1) / ns);     // <= kGramSliceRows, balanced
     g.rows = std::min<int64_t>(g.rows, std::max<int64_t>(1, kBlasMaxElems / std::max<int64_t>(1, ld)));
     g.full = n_rows / g.rows;
     g.tail = n_rows - g.full * g.rows;
