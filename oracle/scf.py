@@ -9,7 +9,8 @@ drops below 1e-4 Ry.
 
 Readings where the paper is silent (all potentials in Ha, lengths in bohr):
 * occupations f_i = 2 for the N_e / 2 lowest Ritz states, rho = sum f X^2 / h^3
-  with X^T X = I;
+  with X^T X = I; the output density of a step is scaled to hold N_e
+  electrons (h^3 sum rho_out = N_e), which orthonormal columns give already;
 * Hartree potential from the same 12th-order stencil, -L V = 4 pi rho on the
   inside points; stencil points outside the sphere take the multipole
   expansion (l <= 4, real solid harmonics about the grid origin) of rho;
@@ -268,6 +269,7 @@ def scf_step(H: Hamiltonian, nbr: np.ndarray, st: ScfState, n_electrons: int, de
         st.a, st.a0 = float(lam[-1]), float(lam[0])
     st.X = X
     rho_out = density(X, n_occ, g.h)
+    rho_out *= n_electrons / (g.h ** 3 * float(rho_out.sum()))
     vh_out, it2 = hartree(g, H.lap, nbr, rho_out, vh_in)
     _, vxc_out = lda(rho_out)
     sre = sre_ry(g.h, rho_out, (vh_out + vxc_out) - (vh_in + vxc_in), n_electrons)

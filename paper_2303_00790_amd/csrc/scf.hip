@@ -671,6 +671,21 @@ static void scf_step_t(chf_scf* S, T* X, int64_t ldx, T* W, int64_t ldw, chf_scf
     rep->chol_fallbacks = fb_total;
     // output density and its potentials (warm start: V_H of rho_in)
     density_t<T>(H, X, ldx, n_occ, S->f(F_RHOO), s);
+    {
+        // the output density holds the electron count, h^3 sum rho_out =
+        // N_e.  FP64 blocks are orthonormal to rounding (a change of ~1e-14);
+        // FP32 blocks only to the accumulation error of their FP32 Gram
+        // products, whose systematic part would otherwise add charge and
+        // shift the whole potential.
+        const int nb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)));
+        ctx->red.ensure(size_t(nb) * sizeof(double));
+        sum_partial_kernel<<<nb, 256, 0, s>>>(n, S->f(F_RHOO), ctx->red.as<double>());
+        LAUNCH_CHECK();
+        const double q = h3 * sum_host(ctx, nb, s);
+        if (!(q > 0)) fail(CHF_ENONFINITE, "scf_step: the output density vanishes");
+        scale_kernel<<<nblk(n), 256, 0, s>>>(n, double(S->prm.n_electrons) / q, S->f(F_RHOO));
+        LAUNCH_CHECK();
+    }
     HIP_CHECK(hipMemcpyAsync(S->f(F_VHO), S->f(F_VH), size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
     int it2 = hartree_solve(H, ctx, S->f(F_RHOO), S->f(F_VHO), S->prm.cg_rtol, 20000, s);
     lda_t(n, S->f(F_RHOO), nullptr, S->f(F_VXCO), s);
