@@ -55,6 +55,36 @@ def test_gram_f32(system, n, m):
     assert np.array_equal(S.cpu().numpy(), S.cpu().numpy().T)
 
 
+def test_gram_f32_wide_block_norms_unbiased(system):
+    """FP32 Gram of a wide block over many rows (1,048,576 x 8192, unit
+    columns): the diagonal, the columns' squared norms, is what FP32
+    Cholesky-QR leaves in the length of every column and so in the charge of
+    the SCF density.  The FP32 MFMA sums of the BLAS kernels come out low by
+    an amount that grows with the rows one sum runs over (measured on the
+    MI355X: -8.6e-6 relative over ~284k-row slices, -3.6e-7 over 8192-row
+    slices); the slices are kept short whatever the width, so the mean
+    error of the diagonal stays below 1e-6 (a long-slice Gram fails)."""
+    B = system["B"]
+    n, m = 1 << 20, 8192
+    print(f"case: FP32 Gram {n} x {m}", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    X = torch.randn((n, m), generator=gen, dtype=torch.float32, device="cuda")
+    true = torch.empty(m, dtype=torch.float64, device="cuda")
+    for c in range(0, m, 512):
+        true[c:c + 512] = (X[:, c:c + 512].double() ** 2).sum(0)
+    X /= true.sqrt().float()[None, :]
+    for c in range(0, m, 512):
+        true[c:c + 512] = (X[:, c:c + 512].double() ** 2).sum(0)
+    S = torch.empty((m, m), dtype=torch.float64, device="cuda")
+    B.gram(system["ctx"], X, X, S)
+    d = (torch.diagonal(S) - true).cpu().numpy()
+    del X, S
+    torch.cuda.empty_cache()
+    print(f"diagonal error: mean {d.mean():.3e}, max |.| {np.abs(d).max():.3e}")
+    assert abs(d.mean()) < 1e-6 and np.abs(d).max() < 3e-6
+
+
 def test_lanczos_bound(system):
     s = system
     v0 = random_block(s["g"].n, 1, 3001)[:, 0]
