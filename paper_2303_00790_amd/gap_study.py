@@ -6,6 +6,7 @@ against h = 0.7 bohr).
     python -m paper_2303_00790_amd.gap_study --diam 1.0 1.5 2.0 2.5 3.0 --h2 0.9 --out gap.json
     python -m paper_2303_00790_amd.gap_study --diam 5.0 --seed0 30007 --h2 0.9 --out gap5.json
     python -m paper_2303_00790_amd.gap_study --merge gap.json gap5.json --out gap_all.json
+    python -m paper_2303_00790_amd.gap_study --diam 5.0 --seed0 30007 --h2 0.9 --rho-in rho5.npy --out gap5.json
 
 Each cluster (seed seed0 + i, position noise 0.02 angstrom) is converged by
 the library's SCF to SRE < 1e-4 Ry in the mixed-precision mode; the
@@ -13,6 +14,9 @@ eigenvalues, HOMO-LUMO gap and DOS (0.1 eV bins, HOMO at 0) are recorded, the
 gap is fitted, and with --h2 every cluster is converged again at the second
 spacing and the two spectra compared.  --merge joins the cluster lists of
 several runs (same spacing, precision and pseudopotential) and refits.
+--rho-in starts the first cluster's SCF at spacing --h from a stored density
+(a pre-converged one, to split a long SCF); the second spacing starts from
+the superposition.
 """
 from __future__ import annotations
 
@@ -25,12 +29,22 @@ import time
 import numpy as np
 
 
-def converge(cluster, pp, h: float, dtype: str, degree: int, log):
+def converge(cluster, pp, h: float, dtype: str, degree: int, log, rho_in=None):
+    """The SCF of one cluster at spacing h from the superposition start, or
+    from rho_in (.npy of the inside-point values in curve order, made on the
+    same grid)."""
     import torch
     from . import scf as S
     st = S.setup(cluster, pp, h=h, dtype=dtype, degree=degree)
     H = st["H"]
-    rho = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
+    if rho_in:
+        rho = torch.zeros(H.n_rows, dtype=torch.float64, device="cuda")
+        vals = torch.from_numpy(np.load(rho_in)).cuda()
+        if vals.numel() != st["rows"].numel():
+            raise SystemExit(f"gap_study: {rho_in} holds {vals.numel()} points, the grid {st['rows'].numel()}")
+        rho[st["rows"]] = vals
+    else:
+        rho = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
     t0 = time.perf_counter()
     log(f"cluster Si{cluster.n_si}H{cluster.n_h}, h = {h}: {H.n_points} points, {st['M']} states")
     res = S.run(st, rho, max_steps=80, sre_tol_ry=1e-4, log=log)
@@ -59,6 +73,8 @@ def main(argv=None):
     ap.add_argument("--pp", default="", help="model pseudopotential overrides, e.g. r_loc=0.9,h_s=2.0")
     ap.add_argument("--seed0", type=int, default=30000, help="geometry seed of the first diameter")
     ap.add_argument("--merge", nargs="+", default=None, metavar="JSON", help="join earlier runs and refit")
+    ap.add_argument("--rho-in", default=None,
+                    help="start density of the first cluster at spacing --h (.npy, inside points in curve order)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     pp = MODEL_PP
@@ -82,8 +98,9 @@ def main(argv=None):
     rows = []
     for i, d in enumerate(args.diam):
         c = make_cluster(5.0 * d, args.seed0 + i, sigma_angstrom=0.02)
-        r = converge(c, pp, args.h, args.dtype, args.degree, log)
-        row = dict(diam_nm=d, seed=args.seed0 + i, n_si=c.n_si, n_h=c.n_h, n_points=r["n_points"], states=r["M"],
+        start = args.rho_in if i == 0 else None
+        r = converge(c, pp, args.h, args.dtype, args.degree, log, rho_in=start)
+        row = dict(diam_nm=d, seed=args.seed0 + i, start_density=os.path.basename(start) if start else "superposition", n_si=c.n_si, n_h=c.n_h, n_points=r["n_points"], states=r["M"],
                    n_occ=r["n_occ"],
                    steps=r["steps"], converged=r["converged"], energy=r["energy"], seconds=r["seconds"],
                    gap_ev=A.gap_ev(r["eig"], r["n_occ"]))
