@@ -124,12 +124,14 @@ def merge_records(paths, test_path=None) -> dict:
                     "mean_steps_net": float(np.mean([r["steps_net"] for r in rows])),
                     "max_de_per_atom": float(max(r["de_per_atom"] for r in rows))})
     if test_path:
+        # the first cluster of that record is the test case; all its rows are kept
         t = json.load(open(test_path))
         row = t["eval"][0]
         res["test_cluster"] = {"diam_nm": t["eval_diam_nm"], "seed": t["eval_seeds"][0],
                                "highpass_sigma": t["highpass_sigma"], "dtype": t["dtype"],
                                "steps_sad": row["steps_sad"], "steps_net": row["steps_net"],
                                "de_per_atom": row["de_per_atom"]}
+        res["small_clusters"] = {"diam_nm": t["eval_diam_nm"], "seeds": t["eval_seeds"], "eval": t["eval"]}
     return res
 
 

@@ -51,6 +51,7 @@ def test_density_records_merge(tmp_path):
     assert res["train"]["train_clusters"] == 120
     assert res["test_cluster"] == dict(diam_nm=2.5, seed=9, highpass_sigma=8.0, dtype="f64", steps_sad=25,
                                        steps_net=21, de_per_atom=1e-9)
+    assert res["small_clusters"]["seeds"] == [9] and len(res["small_clusters"]["eval"]) == 1
     other = tmp_path / "c.json"
     other.write_text(json.dumps(_eval([4], [(40, 30)], diam=3.0)))
     with pytest.raises(SystemExit):
