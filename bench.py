@@ -149,7 +149,18 @@ def filter_record(B, H, X, W, degree, bounds, steps, warmup, generic, n_pts, nve
             "pass_achieved": pass_gbs, "pass_frac": pass_gbs / HBM_PEAK_GBS}
 
 
-def fp64_record(B, steps: int, warmup: int) -> dict:
+def committed_traffic(path: str, key: str):
+    """HBM bytes per launch from the committed counter runs, only if they
+    were taken on the kernel source as it is now (else None)."""
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(key)
+    if rec and rec.get("source_sha256") == kernel_source_hash():
+        return rec.get("bytes_per_launch")
+    return None
+
+
+def fp64_record(B, steps: int, warmup: int, traffic_path: str = "") -> dict:
     """The FP64 filter on the 3 nm cluster (Si705H300, 593,857 points): one
     128-vector block, degree 12, on the blockwise Hilbert order (tiled kernel,
     and the neighbour-table kernel on the same order) and on the
@@ -181,6 +192,8 @@ def fp64_record(B, steps: int, warmup: int) -> dict:
         out["points"] = H.n_points
         out[name] = filter_record(B, H, X, W, wl.degree, (tmin + 0.1 * (b - tmin), b, a0), steps, warmup, generic,
                                   H.n_points, wl.nvec, 8)
+        if not generic:
+            out[name]["roofline"]["traffic"] = committed_traffic(traffic_path, f"{wl.name}:f64:{wl.nvec}")
         del H, X, W
         torch.cuda.empty_cache()
     return out
@@ -308,11 +321,7 @@ def main():
     kernel = ("hx_generic_kernel" if generic else "hx_tile_kernel")
     # HBM traffic from the committed counter runs, only if they were taken on
     # the kernel source as it is now
-    traffic = None
-    if not generic and os.path.exists(args.traffic):
-        rec = json.load(open(args.traffic)).get(f"{wl.name}:{dtype_name}:{nvec}")
-        if rec and rec.get("source_sha256") == kernel_source_hash():
-            traffic = rec.get("bytes_per_launch")
+    traffic = None if generic else committed_traffic(args.traffic, f"{wl.name}:{dtype_name}:{nvec}")
     out = {
         "metric": "filtered gridpt*vectors/s (Chebyshev filter, one GPU)",
         "value": value,
@@ -342,7 +351,7 @@ def main():
     del X, W
     torch.cuda.empty_cache()
     if not args.no_fp64 and args.workload == "d16nm" and not generic:
-        out["fp64_c2"] = fp64_record(B, max(3, args.steps // 2), 1)
+        out["fp64_c2"] = fp64_record(B, max(3, args.steps // 2), 1, args.traffic)
     learned = os.path.join(ROOT, "results", "learned_density_4nm.json")
     if os.path.exists(learned):
         ld = json.load(open(learned))

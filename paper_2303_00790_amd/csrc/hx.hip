@@ -788,6 +788,13 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
     V (*plane)[400][LANES] = reinterpret_cast<V (*)[400][LANES]>(lds + kCstBytes);
     V (*cst)[2][LANES][2] = reinterpret_cast<V (*)[2][LANES][2]>(lds);
 
+    // XCD-aware tile order, as in the unstaged kernel: each XCD takes a
+    // contiguous run of the tile sequence.  FP32 tiles run block-major (a
+    // block's vector chunks adjacent, sharing its tables and staged
+    // coefficients in L2); FP64 tiles run chunk-major (each chunk's blocks
+    // along the Hilbert curve, so the tiles in flight on an XCD are
+    // neighbouring blocks whose halos overlap), which measured faster for
+    // the FP64 kernel, whose traffic sits near the copy ceiling.
     const int64_t ntiles = n_blocks * n_chunks;
     const int64_t per_xcd = (ntiles + 7) / 8;
     const int64_t tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -809,8 +816,9 @@ __global__ void __launch_bounds__(1024) hx_tile_kernel(int64_t n_blocks, int n_c
         return make_rsrc(nb >= 0 ? X + int64_t(nb) * kBlockPts * ldx : X, nb >= 0 ? blk_bytes : 0u);
     };
 
-    const int64_t blk = tile / n_chunks;
-    const int chunk = int(tile - blk * n_chunks);
+    constexpr bool chunk_major = sizeof(T) == 8;
+    const int64_t blk = chunk_major ? tile % n_blocks : tile / n_chunks;
+    const int chunk = chunk_major ? int(tile / n_blocks) : int(tile - blk * n_chunks);
     int32_t nbs[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) nbs[f] = bnb[6 * blk + f];
