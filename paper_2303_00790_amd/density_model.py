@@ -40,12 +40,20 @@ def box_geometry(H) -> tuple[int, int]:
     return D, n_r + (D - (2 * n_r + 1)) // 2
 
 
-def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, max_steps: int = 60, log=None):
+def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, max_steps: int = 60, log=None,
+                     start_net=None, start_highpass: float = 0.0):
+    """One training sample: the SCF converged from the superposition start,
+    or from start_net's predicted start (the fixed point, and so the label,
+    is the same; only the number of steps to reach it changes)."""
     import torch
     st = S.setup(cluster, pp, dtype=dtype)
     H = st["H"]
-    rho_sad = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
-    res = S.run(st, rho_sad.clone(), max_steps=max_steps, sre_tol_ry=sre_tol_ry, log=log)
+    if start_net is not None:
+        rho_sad, rho0 = predicted_start(start_net, H, cluster, start_highpass)
+    else:
+        rho_sad = H.sad_density(cluster.pos, cluster.species, cluster.n_electrons)
+        rho0 = rho_sad.clone()
+    res = S.run(st, rho0, max_steps=max_steps, sre_tol_ry=sre_tol_ry, log=log)
     rho_conv = torch.zeros_like(rho_sad)
     st["scf"].fields(rho_conv)
     D, off = box_geometry(H)
@@ -57,12 +65,13 @@ def converged_sample(cluster, pp, dtype: str = "f32", sre_tol_ry: float = 1e-4, 
 
 
 def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: float = 0.05, log=print,
-                 dtype: str = "f64", budget_s: float | None = None):
+                 dtype: str = "f64", budget_s: float | None = None, start_net=None, start_highpass: float = 0.0):
     """Training data: the superposition start and the correction to the SCF
     density converged by the FP64 path (dtype) on up to n seeded random
     clusters; with budget_s, no new cluster is started once that many seconds
     have passed (the data stay in device memory, so generation and training
-    share one session)."""
+    share one session).  start_net (an earlier network) only shortens the
+    SCFs that make the labels."""
     from synth.cluster import make_cluster
     rng = np.random.default_rng(seed0)
     data = []
@@ -76,7 +85,8 @@ def make_dataset(n: int, seed0: int, diam_nm: tuple[float, float], pp, sigma: fl
         if c.n_atoms == 0:
             continue
         t0 = time.perf_counter()
-        smp, res = converged_sample(c, pp, dtype=dtype, log=log)
+        smp, res = converged_sample(c, pp, dtype=dtype, log=log, start_net=start_net,
+                                    start_highpass=start_highpass)
         data.append(smp)
         log(f"train cluster {i}: d={d:.2f} nm Si{c.n_si}H{c.n_h} box {smp.D}^3 scf steps {res.steps} "
             f"converged {res.converged} ({time.perf_counter() - t0:.1f} s)")

@@ -48,6 +48,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--params-out", default=None)
     ap.add_argument("--params-in", default=None, help="skip data and training; evaluate these weights")
+    ap.add_argument("--label-start", default=None, metavar="NPY",
+                    help="weights of an earlier network whose (high-passed) prediction starts the SCFs that make "
+                         "the training labels; the labels are the same converged densities, reached in fewer steps")
     ap.add_argument("--merge", nargs="+", default=None, metavar="JSON",
                     help="combine a training record and evaluation records (same weights, same diameter) into --out")
     ap.add_argument("--test-record", default=None, metavar="JSON",
@@ -71,8 +74,15 @@ def main(argv=None):
         res["params_in"] = os.path.basename(args.params_in)
     else:
         t0 = time.perf_counter()
+        start_net = None
+        if args.label_start:
+            start_net = B.DensityNet(args.channels, seed=2)
+            start_net.set_params(np.load(args.label_start).astype(np.float32))
+            res["label_start"] = {"params": os.path.basename(args.label_start), "highpass_sigma": args.highpass}
         data = DM.make_dataset(args.train, 10000, tuple(args.train_diam), MODEL_PP, sigma=0.05, log=log,
-                               dtype=args.dtype, budget_s=args.data_budget)
+                               dtype=args.dtype, budget_s=args.data_budget, start_net=start_net,
+                               start_highpass=args.highpass)
+        del start_net
         t_data = time.perf_counter() - t0
         t1 = time.perf_counter()
         losses = DM.train(net, data, args.steps, patch=args.patch, lr=args.lr, log=log)
