@@ -224,8 +224,9 @@ int lanczos_bound(chf_ham* ham, chf_ctx* ctx, const double* v0_dev, int k, doubl
                   void* stream);
 
 /* S = A^T B for row-major blocks A [n_rows][lda] (m columns) and B [n_rows][ldb]
- * (n columns): products of row slices (at least 4096 rows each) accumulated on
- * MFMA in the block precision (rocBLAS), the slice partials added in FP64 in
+ * (n columns): products of row slices (at most 8192 rows each, whatever the
+ * width, so that no sum in the block precision runs over more rows) accumulated
+ * on MFMA in the block precision (rocBLAS), the slice partials added in FP64 in
  * slice order.  S_dev is FP64 row-major [m][lds].  With A == B and m == n the
  * upper triangle is summed and mirrored, so S is exactly symmetric. */
 int gram(chf_ctx* ctx, chf_dtype dtype, const void* A_dev, int64_t lda, const void* B_dev,
@@ -364,7 +365,10 @@ int chf_scf_destroy(chf_scf* scf);
  * computational-details paragraph: LDA-PZ, four ChFSI iterations in the first
  * step and one in each later step, SRE stopping criterion): V_eff from rho_in,
  * Lanczos bound, ChFSI iterations on X (filter, Cholesky-QR, Rayleigh-Ritz),
- * rho_out, SRE, Harris-Foulkes energy, Anderson mixing of rho_in.  eig_host
+ * rho_out (scaled to hold the n_electrons electrons: h^3 sum rho_out = N_e,
+ * which orthonormal FP64 columns give to rounding; FP32 columns only up to
+ * the accumulation error of their Gram products), SRE, Harris-Foulkes
+ * energy, Anderson mixing of rho_in; CHF_ENONFINITE if rho_out vanishes.  eig_host
  * (may be NULL) receives the nvec Ritz values.  X: [n_rows][ldx] in
  * filter_dtype, caller-owned and updated in place; work: [n_rows][ldw],
  * ldw >= 1 (the filter and Rayleigh-Ritz work in column blocks of
