@@ -61,11 +61,14 @@ def alg_bytes_per_launch(n_points: int, nvec: int, elem_bytes: int, degree: int)
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 of the H X kernel source (the counters in profiles/ name it)."""
+    """SHA-256 of the H X kernel source without its // comments and blank
+    lines (the counters in profiles/ name it; an edit of the comments alone
+    leaves the kernels, and so the counters, unchanged)."""
     import hashlib
     src = os.path.join(ROOT, "paper_2303_00790_amd", "csrc", "hx.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    with open(src, encoding="utf-8") as f:
+        code = [line.split("//", 1)[0].rstrip() for line in f]
+    return hashlib.sha256("\n".join(line for line in code if line).encode()).hexdigest()
 
 
 def cpu_baseline(degree: int, sample: str = "auto", workload: str = "d16nm") -> dict:

@@ -11,10 +11,15 @@
 //  * hx_generic       per-row neighbour-table stencil + V + KB scatter, with
 //                     the Chebyshev three-term update fused into the store:
 //                     Y = alpha (H X - c X) - beta Z  (Z may alias Y).
-//  * hx_tiled         the same operator on the Hilbert-blocked layout: one
+//  * hx_tile          the same operator on the Hilbert-blocked layout: one
 //                     workgroup per (8^3 block, 32-float / 16-double vector
-//                     chunk), z-march with a 13-deep register window per
-//                     column, x/y halos staged in LDS (double-buffered).
+//                     chunk), z-march with a 20-deep register window per
+//                     column, x/y halos staged in LDS (double-buffered), the
+//                     block atoms' KB coefficients staged in LDS and the KB
+//                     term applied inside the march.
+//  * hx_tiled         the same tile without staging, for blocks touched by
+//                     more than kMaxBlockAtoms projector atoms, Laplacian-only
+//                     products and Hamiltonians without projectors.
 #include <atomic>
 #include <cmath>
 #include <mutex>
