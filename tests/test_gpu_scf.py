@@ -167,6 +167,33 @@ def test_scf_step_rejects_overlapping_work(si35):
     assert e.value.code == -1
 
 
+def test_mixed_scf_keeps_the_electron_count(si35):
+    """The output density of a step is scaled to hold N_e electrons, so
+    rho_in, an Anderson combination of such densities and of the normalised
+    superposition start, holds N_e after every step of a mixed-precision SCF
+    (FP32 filter and Gram).  Without the scaling it would carry the column
+    norm error that FP32 Cholesky-QR leaves, ~1e-7 relative."""
+    s = si35
+    B = s["B"]
+    c = s["c"]
+    ne = c.n_electrons
+    M = n_states(ne)
+    eii = OS.ion_energy(c.pos, s["pp"].charges(c.species))
+    prm = B.ScfParams(ne, M, 10, 4, 1, 10, B.CHF_F32, B.CHF_F32, 6, 0.3, 1e-12, eii)
+    rho0 = s["Hg"].sad_density(c.pos, c.species, ne)
+    v0 = to_rows(s, random_block(s["g"].n, 1, 3005)[:, 0], torch.float64)
+    scf = B.Scf(s["Hg"], s["ctx"], prm, rho0, v0)
+    X = to_rows(s, random_block(s["g"].n, M, 2005), torch.float32)
+    W = torch.zeros((s["Hg"].n_rows, M), dtype=torch.float32, device="cuda")
+    h3 = 0.7 ** 3
+    rho = torch.zeros(s["Hg"].n_rows, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        scf.step(X, W)
+        scf.fields(rho)
+        q = h3 * float(rho.sum())
+        assert abs(q - ne) < 1e-11 * ne, (q, ne)
+
+
 def test_checkpoint_resume_is_bit_exact(si35):
     """Saving the SCF state after three steps and resuming it in a fresh
     handle reproduces the fourth step of the uninterrupted run exactly."""
