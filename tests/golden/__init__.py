@@ -1,5 +1,6 @@
 """Readers for the fixtures in this folder: numbers the paper prints, transcribed
-by hand with their citation in each file's header.  Nothing here is computed."""
+by hand with their citation in each file's header.  The one computed fixture,
+scf_si35_oracle.json, is written by make_scf_si35.py from the oracle alone."""
 from __future__ import annotations
 
 from pathlib import Path

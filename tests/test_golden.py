@@ -53,3 +53,17 @@ def test_gap_fit_constants_are_physical():
     # small-cluster fits (1.1 to 1.39) and the effective-mass limit of 2, as the text argues
     assert 0 < FIG["gap_offset_ev"] < 1.2 and 1.39 < FIG["gap_exponent"] < 2.0
     assert 0.99 < FIG["gap_fit_r2"] < 1.0
+
+
+def test_oracle_scf_reference_is_consistent():
+    # the computed fixture: occupied eigenvalues ascending, HOMO the last of
+    # them, a gap to the LUMO, one state per electron pair, converged below
+    # the threshold the generator uses
+    import json
+    from pathlib import Path
+    ref = json.loads((Path(__file__).resolve().parent / "golden" / "scf_si35_oracle.json").read_text())
+    e = ref["eig_occ_ha"]
+    assert len(e) == ref["cluster"]["n_electrons"] // 2
+    assert all(a <= b for a, b in zip(e, e[1:]))
+    assert e[-1] == ref["homo_ha"] < ref["lumo_ha"]
+    assert ref["sre_ry"] < 1e-8 and ref["states"] >= len(e)
