@@ -703,6 +703,11 @@ int rayleigh_ritz(chf_ham* H, chf_ctx* ctx, chf_dtype dtype, void* X, int64_t ld
         check_ctx_block(ctx, dtype, X, ldx, nvec, "rayleigh_ritz X");
         check_ctx_block(ctx, dtype, work, ldw, std::min(nvec, int(ldw)), "rayleigh_ritz work");
         if (!(H->dtypes & (dtype == CHF_F64 ? 2 : 1))) fail(CHF_EINVAL, "rayleigh_ritz: handle not built for dtype");
+        // an orthonormal block has at most as many columns as grid points
+        // (this also keeps each row panel of the in-place rotation, m values
+        // per row, within the work block's n_rows x ldw values)
+        if (int64_t(nvec) > H->grid.n)
+            fail(CHF_EINVAL, "rayleigh_ritz: nvec %d exceeds the %lld grid points", nvec, (long long)H->grid.n);
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (dtype == CHF_F64)
             rayleigh_ritz_t<double>(H, ctx, static_cast<double*>(X), ldx, nvec, eig_host, static_cast<double*>(work), ldw, s);

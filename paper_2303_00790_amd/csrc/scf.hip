@@ -856,6 +856,8 @@ int chf_scf_create(chf_ham* H, chf_ctx* ctx, const chf_scf_params* prm, const do
         *out = nullptr;
         if (prm->n_electrons < 2 || prm->n_electrons % 2) fail(CHF_EINVAL, "chf_scf_create: need an even electron count");
         if (prm->nvec <= prm->n_electrons / 2) fail(CHF_EINVAL, "chf_scf_create: nvec must exceed the occupied count");
+        if (int64_t(prm->nvec) > H->grid.n)
+            fail(CHF_EINVAL, "chf_scf_create: nvec exceeds the grid points (no orthonormal block of that width)");
         if (prm->degree < 1 || prm->first_iters < 1 || prm->later_iters < 1) fail(CHF_EINVAL, "chf_scf_create: bad schedule");
         if (prm->lanczos_k < 2 || prm->lanczos_k > 64) fail(CHF_EINVAL, "chf_scf_create: lanczos_k in [2, 64]");
         if (prm->filter_dtype != CHF_F32 && prm->filter_dtype != CHF_F64) fail(CHF_EINVAL, "chf_scf_create: bad filter dtype");

@@ -212,6 +212,22 @@ def test_rayleigh_ritz_narrow_work_matches_full_width(system, dtype, tol):
     assert float((da - db * sign).abs().max() / da.abs().max()) < (1e-10 if dtype == torch.float64 else 1e-3)
 
 
+def test_rayleigh_ritz_rejects_more_vectors_than_grid_points():
+    # a block wider than the grid cannot be orthonormal; the call refuses it
+    # before any device work (it would also not fit the rotation's row panels
+    # in a one-column work block)
+    from paper_2303_00790_amd import binding as B
+    from synth.workloads import MODEL_PP
+    H = B.Hamiltonian(np.zeros((1, 3)), np.array([1], np.int32), MODEL_PP, 0.7, 2.5, B.ORDER_HILBERT)
+    assert H.n_points < H.n_rows
+    ctx = B.Context(0)
+    X = torch.zeros((H.n_rows, H.n_points + 1), dtype=torch.float64, device="cuda")
+    W = torch.zeros((H.n_rows, 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.ChfError) as e:
+        B.rayleigh_ritz(H, ctx, X, W)
+    assert e.value.code == -1 and "grid points" in str(e.value)
+
+
 def test_orthonormalize_rank_deficient_falls_back(system):
     s = system
     X = random_block(s["g"].n, 32, 2402)
