@@ -288,8 +288,10 @@ int orthonormalize(chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int6
  * rows, in place (the work block holds one panel at a time; Q rounded to
  * FP32 for an FP32 block).  eig_host [nvec] ascending.  So the work block
  * can be much narrower than X: at 7552 FP64 states a 256-wide work block is
- * 1/30 of X.  Errors: CHF_EINVAL, CHF_ENOTCONV (eigensolver),
- * CHF_ENONFINITE (a Ritz value is NaN or Inf; X is then unchanged). */
+ * 1/30 of X.  Errors: CHF_EINVAL (null argument, ldx < nvec, ldw < 1, X and
+ * work overlapping, nvec above the grid's point count, a handle without this
+ * dtype), CHF_ENOTCONV (eigensolver), CHF_ENONFINITE (a Ritz value is NaN or
+ * Inf; X is then unchanged). */
 int rayleigh_ritz(chf_ham* ham, chf_ctx* ctx, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec,
                   double* eig_host, void* work_dev, int64_t ldw, void* stream);
 
@@ -355,7 +357,11 @@ typedef struct {
 
 /* SCF state: owns rho_in, V_H, the Anderson history and the filter bounds;
  * X and the work block stay caller-owned.  rho0_dev ([n_rows]) is the
- * initial density, v_lanczos_dev ([n_rows]) the fixed Lanczos start vector. */
+ * initial density, v_lanczos_dev ([n_rows]) the fixed Lanczos start vector.
+ * CHF_EINVAL for inconsistent parameters: an odd electron count, nvec not
+ * above the occupied count or above the grid's point count, a bad schedule,
+ * mixing, tolerance or dtype, an FP64 filter with an FP32 Gram, a handle
+ * without FP64 or without the filter's dtype. */
 int chf_scf_create(chf_ham* ham, chf_ctx* ctx, const chf_scf_params* params, const double* rho0_dev,
                    const double* v_lanczos_dev, chf_scf** out);
 int chf_scf_destroy(chf_scf* scf);
