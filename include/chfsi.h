@@ -174,9 +174,14 @@ int ham_apply(chf_ham* ham, chf_dtype dtype, const void* X_dev, int64_t ldx, voi
  * contents on return are unspecified).  The vectors are independent, so a
  * work block narrower than nvec is used column block by column block
  * (min(nvec, ldw) vectors, rounded down to a multiple of 64 when ldw < nvec
- * and ldw >= 64).  Requires a < b and a0 < a; 1 <= degree <= 1000.  Errors:
- * CHF_EINVAL (null block, ld < nvec, bounds, X and work overlapping),
- * CHF_EHIP. */
+ * and ldw >= 64, else to a multiple of 4 when ldw >= 4).  The tiled kernel of
+ * the Hilbert layout takes blocks whose width and leading dimensions are
+ * multiples of 2 (FP32) and 8-byte aligned; other blocks, such as the 1- to
+ * 3-column blocks of a work block with ldw < 4, take the neighbour-table
+ * kernel, which needs a handle built with keep_nbr.  Requires a < b and
+ * a0 < a; 1 <= degree <= 1000.  Errors: CHF_EINVAL (null block, ld < nvec,
+ * bounds, X and work overlapping), CHF_EUNSUPPORTED (a block only the
+ * neighbour-table kernel takes, on a handle without the table), CHF_EHIP. */
 int chebyshev_filter(chf_ham* ham, chf_dtype dtype, void* X_dev, int64_t ldx, int nvec, int degree,
                      double a, double b, double a0, void* work_dev, int64_t ldw, void* stream);
 
